@@ -1,0 +1,264 @@
+/*
+ * fdwave.h -- C ABI of the MI355X (gfx950) acoustic finite-difference sweep
+ * library, libfdwave.so.
+ *
+ * The library advances the damped, second-order-in-time acoustic wave equation
+ *     m u_tt + damp u_t - Lap(u) = source,    m = 1 / v^2,
+ * with the leapfrog update of the paper's Devito-generated stencil (Sec. 6.3.1,
+ * Fig. "acoustic_devito"; the same update is the body of the time-tiled loop of
+ * Sec. 5.5, Fig. "tiled_256"):
+ *     u^{n+1} = ((dt damp - 2m) u^{n-1} + 4m u^n + 2 dt^2 L_h u^n) / (dt damp + 2m)
+ * where L_h is the star Laplacian of space order so (2, 4, ..., 16), whose
+ * weights are the closed-form central second-difference coefficients.  Points
+ * outside the grid are zero (the paper's never-written ghost cells).  The GPU
+ * evaluates the same update in the algebraically equal form
+ *     u^{n+1} = (2 u^n + (eta - 1) u^{n-1} + q L_h u^n) / (1 + eta),
+ *     q = v^2 dt^2,  eta = dt damp v^2 / 2,
+ * in FP32 with one fixed per-point operation order shared by every kernel
+ * variant, so that the untiled, space-tiled and time-blocked kernels return
+ * bit-identical fields.
+ *
+ * Time blocking (the paper's contribution, Secs. 5.2-5.4 and 7.1): a kernel may
+ * advance T >= 2 time levels per pass over HBM.  Legality comes from skewing
+ * each level by the stencil radius M = so/2 (Sec. 5.2: skew by the largest
+ * negative dependence distance), which the streaming kernels realise as a lag
+ * of M planes per level along the streamed axis plus an overlapped halo of
+ * M (T - 1) cells in the two tiled axes.
+ *
+ * Readings the paper leaves open (it only names source and receiver loops and
+ * a damp array, Sec. 6.2 shell log and Sec. 6.3.1):
+ *   * sources are injected in the step producing u^{n+1}:
+ *       u^{n+1}(s) += 2 dt^2 w[n][s] / (dt damp(s) + 2 m(s));
+ *   * receivers record the new level on grid nodes: d[n][r] = u^{n+1}(r);
+ *   * sponge: damp(i) = sum_a d0_a (delta_a / L)^2 with delta_a the number of
+ *     cells into the outer L-cell layer of axis a (0 in the interior and at the
+ *     layer's inner edge) and d0_a = 1.5 ln(1000) / (vref L h_a)  [s/m^2];
+ *   * stability: Courant number v_max dt / h_min must not exceed
+ *     2 / sqrt(ndim * S) with S = -c_0 - 2 sum_k (-1)^k c_k.
+ *
+ * Memory layout of every field: dense FP32, C order over the ndim axes, the
+ * last axis contiguous (the paper's z loop is the innermost, vectorised one).
+ * A 3-D grid has axes (x, y, z); 2-D grids are treated as 3-D with a unit
+ * middle axis, 1-D grids as 3-D with two unit leading axes.
+ *
+ * Ownership: the caller owns every buffer.  Device pointers must stay valid
+ * until the work enqueued on `stream` has completed.  The library never
+ * allocates device memory on these paths: all scratch lives in the caller's
+ * workspace (size from fd_workspace_size).  Host pointers (point indices) are
+ * read during the call only.
+ *
+ * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL is
+ * the default stream) and returns without waiting, except (i) the stability
+ * check, which reads back max(v) (skip it with FD_FLAG_NO_CFL_CHECK), and
+ * (ii) fd_gradient when `misfit` is non-NULL, which waits for the misfit.
+ *
+ * Errors: every entry point returns 0 (FD_OK) or a negative FD_E* code; no
+ * C++ exception crosses the ABI.  On error nothing further is enqueued, but
+ * work enqueued before the failing check may still run.
+ */
+#ifndef FDWAVE_H
+#define FDWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define FD_OK 0
+#define FD_EINVAL (-1)        /* bad descriptor, pointer, size or option */
+#define FD_ECFL (-2)          /* dt beyond the leapfrog stability limit */
+#define FD_EDOM (-3)          /* a source or receiver index outside the grid */
+#define FD_EWORKSPACE (-4)    /* workspace NULL or smaller than fd_workspace_size */
+#define FD_ENOMEM (-5)        /* a host-side allocation failed */
+#define FD_EHIP (-6)          /* a HIP runtime call failed */
+#define FD_ENONFINITE (-7)    /* v has a NaN/Inf/non-positive entry, or (with
+                                 FD_FLAG_CHECK_FINITE) the traces are not finite */
+#define FD_EUNSUPPORTED (-8)  /* no compiled kernel for the requested options */
+
+/* ------------------------------------------------------------------ variants */
+#define FD_VARIANT_AUTO 0    /* autotuner / cached choice */
+#define FD_VARIANT_NAIVE 1   /* untiled: one thread per point, neighbours from memory */
+#define FD_VARIANT_STREAM 2  /* space-tiled: (y,z) tile per workgroup, x streamed
+                                through a register queue, y/z neighbours via LDS */
+#define FD_VARIANT_TBLOCK 3  /* time-blocked streaming: T levels per HBM pass */
+
+/* ------------------------------------------------------------------ flags */
+#define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */
+#define FD_FLAG_CHECK_FINITE 2u   /* read back the traces and fail on NaN/Inf */
+#define FD_FLAG_NO_XCD_REMAP 4u   /* keep the hardware workgroup order (for A/B timing) */
+
+/* ------------------------------------------------------------------ ops for workspace sizing */
+#define FD_OP_FORWARD 0
+#define FD_OP_ADJOINT 1
+#define FD_OP_GRADIENT 2
+#define FD_OP_VJP 3
+
+/* Grid: extents, spacing, space order and sponge. */
+typedef struct fd_grid {
+    int32_t ndim;         /* 1, 2 or 3 */
+    int32_t space_order;  /* 2, 4, 6, ..., 16 */
+    int64_t n[3];         /* points per axis (first ndim used), last axis contiguous */
+    double h[3];          /* spacing per axis in metres, > 0 */
+    int32_t sponge;       /* sponge width L in cells, 0 = none (2 L <= n[a]) */
+    int32_t reserved;     /* must be 0 */
+    double sponge_vref;   /* velocity (m/s) setting the sponge strength, > 0 if sponge > 0 */
+} fd_grid;
+
+/* Time axis. */
+typedef struct fd_time {
+    int64_t nt;  /* number of steps, >= 0 */
+    double dt;   /* step in seconds, > 0 */
+} fd_time;
+
+/* Point set (sources or receivers) on grid nodes. */
+typedef struct fd_points {
+    int32_t n;           /* number of points, >= 0 */
+    int32_t reserved;    /* must be 0 */
+    const int32_t *idx;  /* HOST, [n][ndim] grid indices (may be NULL if n == 0) */
+    const float *amp;    /* DEVICE, [nt][n] time samples: source wavelet (forward),
+                            injected residual (adjoint), observed data or trace
+                            cotangent (gradient / vjp); unused where not listed */
+} fd_points;
+
+/* Execution options; zero-initialised options mean "automatic". */
+typedef struct fd_options {
+    int32_t variant;     /* FD_VARIANT_*; 0 = automatic */
+    int32_t tile[3];     /* {planes per workgroup along x, tile rows along y,
+                            rows per thread}; 0 = automatic */
+    int32_t tblock;      /* time levels per pass for FD_VARIANT_TBLOCK (2..4); 0 = auto */
+    int32_t ckpt_every;  /* gradient checkpoint interval k in steps; 0 = auto (50) */
+    uint32_t flags;      /* FD_FLAG_* */
+    int32_t reserved;    /* must be 0 */
+} fd_options;
+
+/*
+ * Bytes of device workspace an operation needs (FD_OP_*).  src/rec give the
+ * point counts (amp is not read); opts may be NULL.  Returns 0 on invalid input.
+ */
+size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_points *src,
+                         const fd_points *rec, const fd_options *opts, int op);
+
+/*
+ * Forward sweep (Sec. 6.3.1 update, nt steps).
+ *   v        DEVICE [N] velocity in m/s (read only).
+ *   src      point sources; src->amp DEVICE [nt][ns] raw wavelet samples w[n].
+ *   rec      receivers; positions only.
+ *   rec_out  DEVICE [nt][nr] receiver traces d[n][r] = u^{n+1}(r); may be NULL if nr == 0.
+ *   u_state  DEVICE [2][N] or NULL.  On entry (u^0, u^{-1}); on return
+ *            (u^nt, u^{nt-1}).  NULL means a zero initial state and no state out.
+ *   workspace/ws_bytes  DEVICE scratch of at least fd_workspace_size(..., FD_OP_FORWARD).
+ *   opts     may be NULL.   stream  hipStream_t or NULL.
+ * Returns FD_OK or FD_EINVAL / FD_EDOM / FD_ECFL / FD_ENONFINITE / FD_EWORKSPACE /
+ * FD_EUNSUPPORTED / FD_EHIP.
+ */
+int fd_forward(const fd_grid *grid, const fd_time *time, const float *v,
+               const fd_points *src, const fd_points *rec, float *rec_out, float *u_state,
+               void *workspace, size_t ws_bytes, const fd_options *opts, void *stream);
+
+/*
+ * Adjoint sweep: the transpose of the linear map F: w -> d that fd_forward
+ * realises for a zero initial state.  With step k written as
+ *   A u^k - B u^{k-1} - C u^{k-2} = 2 dt^2 P_s^T w^{k-1},
+ *   A = diag(2m + dt damp), B = 4m + 2 dt^2 L_h (symmetric), C = diag(dt damp - 2m),
+ * the adjoint solves lambda^k = A^{-1}(B lambda^{k+1} + C lambda^{k+2} + P_r^T y[k-1])
+ * backward from lambda^{nt+1} = lambda^{nt+2} = 0, i.e. the same stencil update
+ * run in reversed time, and returns (F^T y)[k-1][s] = 2 dt^2 lambda^k(s).
+ *   rec->amp DEVICE [nt][nr] the traces y injected at the receivers.
+ *   src_out  DEVICE [nt][ns] result at the source positions (may be NULL if ns == 0).
+ *   lam_state DEVICE [2][N] or NULL: on return (lambda^1, lambda^2).
+ */
+int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v,
+               const fd_points *src, const fd_points *rec, float *src_out, float *lam_state,
+               void *workspace, size_t ws_bytes, const fd_options *opts, void *stream);
+
+/*
+ * Gradient of the least-squares misfit J = 1/2 sum_{n,r} (d[n][r] - d_obs[n][r])^2
+ * with respect to v, for a zero initial state:
+ *   dJ/dm(x) = -2 sum_{k=1..nt} lambda^k(x) (u^k - 2u^{k-1} + u^{k-2})(x)   (zero-lag
+ *   imaging condition, lambda from fd_adjoint's recurrence driven by the residual),
+ *   dJ/dv = dJ/dm * (-2 / v^3).
+ * Forward wavefields are checkpointed every ckpt_every steps (u^{jk}, u^{jk-1}) and
+ * recomputed segment by segment (the paper's buffered vs saved time dimension,
+ * Sec. 6.3.2, traded through recomputation).  The imaging sum is accumulated
+ * in FP64.
+ *   src->amp DEVICE [nt][ns] source wavelet; rec->amp DEVICE [nt][nr] observed data.
+ *   grad_v   DEVICE [N] FP32 result.
+ *   misfit   HOST double or NULL (non-NULL: the call waits for it).
+ *   residual DEVICE [nt][nr] or NULL: receives d - d_obs.
+ */
+int fd_gradient(const fd_grid *grid, const fd_time *time, const float *v,
+                const fd_points *src, const fd_points *rec, float *grad_v, double *misfit,
+                float *residual, void *workspace, size_t ws_bytes, const fd_options *opts,
+                void *stream);
+
+/*
+ * Vector-Jacobian product of the map v -> d (receiver traces, zero initial
+ * state): grad_v = (dd/dv)^T y for the trace cotangent y = rec->amp DEVICE [nt][nr].
+ * Same checkpointed adjoint-state computation as fd_gradient with the residual
+ * replaced by y (this is what a reverse-mode autodiff backward needs).
+ */
+int fd_vjp(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+           const fd_points *rec, float *grad_v, void *workspace, size_t ws_bytes,
+           const fd_options *opts, void *stream);
+
+/*
+ * Autotuner: times candidate kernels (variant, tile, time-block depth) for a
+ * few steps at this grid's real shape (zero state, no points) on `stream`,
+ * writes the fastest into *inout (fields left 0 are searched, set fields are
+ * kept) and caches it in-process and, if the environment variable
+ * FD_AUTOTUNE_CACHE names a file, in that file keyed by (ndim, n, so, arch).
+ * Synchronises the stream.  workspace must hold
+ * fd_workspace_size(grid, time, NULL, NULL, NULL, FD_OP_FORWARD) for time->nt = 8.
+ */
+int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options *inout, void *workspace,
+                size_t ws_bytes, void *stream);
+
+/* One shot of a batch (all pointers as in fd_forward / fd_gradient). */
+typedef struct fd_shot {
+    fd_grid grid;
+    fd_time time;
+    const float *v;       /* DEVICE [N] */
+    fd_points src;        /* amp: DEVICE [nt][ns] wavelet */
+    fd_points rec;        /* amp: DEVICE [nt][nr] observed data (gradient) */
+    float *rec_out;       /* DEVICE [nt][nr] traces (forward) or NULL */
+    float *grad_v;        /* DEVICE [N] (gradient) or NULL */
+    double misfit;        /* out (gradient) */
+    fd_options opts;      /* per-shot options (variant/tile/tblock; 0 = auto) */
+} fd_shot;
+
+/* Workspace for a batch: the sum over shots, each rounded up to 256 bytes. */
+size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int op);
+
+/*
+ * Batched forward sweeps over shots of uneven grid size and space order.
+ * All shots' time blocks are issued as grouped launches: one launch per
+ * (space order, time-block depth) class per pass covers the tiles of every shot
+ * in that class, its workgroups walking the tile table persistently.  With
+ * flags & FD_BATCH_GRAPH the whole sequence is captured once into a hipGraph
+ * and replayed.  Synchronises the stream (stability checks and graph build).
+ */
+#define FD_BATCH_GRAPH 1u
+int fd_forward_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
+                     uint32_t batch_flags, void *stream);
+
+/* Batched least-squares gradients (each shot as fd_gradient); misfits in shots[i].misfit. */
+int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
+                      uint32_t batch_flags, void *stream);
+
+/* Static text for a status code. */
+const char *fd_strerror(int code);
+
+/* ABI version (major * 100 + minor). */
+int fd_version(void);
+
+/* Writes the kernel configuration the last call on this thread used into *out
+ * (variant, tile, tblock actually run).  Returns FD_OK, or FD_EINVAL if none. */
+int fd_last_config(fd_options *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDWAVE_H */

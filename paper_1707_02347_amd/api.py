@@ -1,0 +1,144 @@
+"""Torch-facing wrappers over the C ABI: device buffers come from PyTorch, the
+work runs on the current HIP stream, every step is done by libfdwave.so.
+
+Shapes: a velocity model ``v`` is a float32 CUDA tensor of 1, 2 or 3 dims
+(last axis contiguous); point indices are integer arrays [n][ndim]; sample
+arrays are float32 CUDA tensors [nt][n].
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _dev_f32(t, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return t.contiguous()
+
+
+def _opts(variant=0, tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0):
+    return L.make_options(variant, tile, tblock, ckpt_every, flags)
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def forward(v, h, so, nt, dt, src_idx=None, src_amp=None, rec_idx=None, u0=None, um1=None,
+            sponge=0, vref=1500.0, variant=0, tile=(0, 0, 0), tblock=0, flags=0):
+    """Forward sweep; returns dict(rec=[nt][nr], u=u^nt, u_prev=u^{nt-1})."""
+    v = _dev_f32(v, "v")
+    shape = tuple(v.shape)
+    nd = len(shape)
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    amp = None if src_amp is None else _dev_f32(src_amp, "src_amp")
+    src = L.Points(src_idx, amp, nd)
+    rec = L.Points(rec_idx, None, nd)
+    o = _opts(variant, tile, tblock, 0, flags)
+    state = torch.zeros((2,) + shape, dtype=torch.float32, device=v.device)
+    if u0 is not None:
+        state[0].copy_(u0)
+    if um1 is not None:
+        state[1].copy_(um1)
+    rec_out = torch.zeros((int(nt), rec.n), dtype=torch.float32, device=v.device)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
+                                 L.FD_OP_FORWARD)
+    ws = _workspace(nbytes, v.device)
+    rc = L.fd_forward(C.byref(grid), C.byref(tm), L._ptr(v), C.byref(src.s), C.byref(rec.s),
+                      L._ptr(rec_out) if rec.n else None, L._ptr(state), L._ptr(ws), ws.numel(),
+                      C.byref(o), L._stream(v.device))
+    L._check(rc, "fd_forward")
+    return {"rec": rec_out, "u": state[0], "u_prev": state[1]}
+
+
+def adjoint(v, h, so, nt, dt, src_idx, rec_idx, rec_amp, sponge=0, vref=1500.0, variant=0,
+            tile=(0, 0, 0), tblock=0, flags=0):
+    """Adjoint sweep: traces rec_amp [nt][nr] -> F^T y at the sources [nt][ns]; also (lambda^1, lambda^2)."""
+    v = _dev_f32(v, "v")
+    shape = tuple(v.shape)
+    nd = len(shape)
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    src = L.Points(src_idx, None, nd)
+    rec = L.Points(rec_idx, _dev_f32(rec_amp, "rec_amp"), nd)
+    o = _opts(variant, tile, tblock, 0, flags)
+    out = torch.zeros((int(nt), src.n), dtype=torch.float32, device=v.device)
+    lam = torch.zeros((2,) + shape, dtype=torch.float32, device=v.device)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
+                                 L.FD_OP_ADJOINT)
+    ws = _workspace(nbytes, v.device)
+    rc = L.fd_adjoint(C.byref(grid), C.byref(tm), L._ptr(v), C.byref(src.s), C.byref(rec.s),
+                      L._ptr(out) if src.n else None, L._ptr(lam), L._ptr(ws), ws.numel(), C.byref(o),
+                      L._stream(v.device))
+    L._check(rc, "fd_adjoint")
+    return {"src": out, "lam": lam}
+
+
+def gradient(v, h, so, nt, dt, src_idx, src_amp, rec_idx, d_obs, sponge=0, vref=1500.0, variant=0,
+             tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0):
+    """Least-squares misfit and dJ/dv (checkpointed adjoint state); returns (J, grad_v, residual)."""
+    v = _dev_f32(v, "v")
+    shape = tuple(v.shape)
+    nd = len(shape)
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    src = L.Points(src_idx, _dev_f32(src_amp, "src_amp"), nd)
+    rec = L.Points(rec_idx, _dev_f32(d_obs, "d_obs"), nd)
+    o = _opts(variant, tile, tblock, ckpt_every, flags)
+    gv = torch.zeros(shape, dtype=torch.float32, device=v.device)
+    res = torch.zeros((int(nt), rec.n), dtype=torch.float32, device=v.device)
+    J = C.c_double(0.0)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
+                                 L.FD_OP_GRADIENT)
+    ws = _workspace(nbytes, v.device)
+    rc = L.fd_gradient(C.byref(grid), C.byref(tm), L._ptr(v), C.byref(src.s), C.byref(rec.s), L._ptr(gv),
+                       C.byref(J), L._ptr(res) if rec.n else None, L._ptr(ws), ws.numel(), C.byref(o),
+                       L._stream(v.device))
+    L._check(rc, "fd_gradient")
+    return float(J.value), gv, res
+
+
+def vjp(v, h, so, nt, dt, src_idx, src_amp, rec_idx, y, sponge=0, vref=1500.0, variant=0,
+        tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0):
+    """(dd/dv)^T y for trace cotangent y [nt][nr]."""
+    v = _dev_f32(v, "v")
+    shape = tuple(v.shape)
+    nd = len(shape)
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    src = L.Points(src_idx, _dev_f32(src_amp, "src_amp"), nd)
+    rec = L.Points(rec_idx, _dev_f32(y, "y"), nd)
+    o = _opts(variant, tile, tblock, ckpt_every, flags)
+    gv = torch.zeros(shape, dtype=torch.float32, device=v.device)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
+                                 L.FD_OP_VJP)
+    ws = _workspace(nbytes, v.device)
+    rc = L.fd_vjp(C.byref(grid), C.byref(tm), L._ptr(v), C.byref(src.s), C.byref(rec.s), L._ptr(gv),
+                  L._ptr(ws), ws.numel(), C.byref(o), L._stream(v.device))
+    L._check(rc, "fd_vjp")
+    return gv
+
+
+def autotune(shape, h, so, dt, device="cuda", sponge=0, vref=1500.0, nt=8, variant=0, tblock=0):
+    """Run the library's autotuner for this grid; returns the chosen options as a dict."""
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    o = _opts(variant, (0, 0, 0), tblock)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(L.make_time(8, dt)), None, None, None,
+                                 L.FD_OP_FORWARD)
+    ws = _workspace(nbytes, device)
+    rc = L.fd_autotune(C.byref(grid), C.byref(tm), C.byref(o), L._ptr(ws), ws.numel(), L._stream(device))
+    L._check(rc, "fd_autotune")
+    return {"variant": o.variant, "tile": tuple(o.tile), "tblock": o.tblock}
+
+
+def last_config():
+    return L.fd_last_config()

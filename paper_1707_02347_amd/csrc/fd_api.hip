@@ -1,0 +1,1244 @@
+// fd_api.hip -- host side of libfdwave.so: validation, planning, workspace
+// layout, the sweep driver, checkpointed adjoint-state gradients, the
+// autotuner and the C ABI declared in include/fdwave.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdwave.h"
+#include "fd_internal.h"
+
+namespace fdw {
+
+bool launch_stream_m1(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m2(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m3(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m4(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m5(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m6(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m7(const KernelKey &, const SweepArgs &, hipStream_t);
+bool launch_stream_m8(const KernelKey &, const SweepArgs &, hipStream_t);
+bool has_stream_m1(const KernelKey &);
+bool has_stream_m2(const KernelKey &);
+bool has_stream_m3(const KernelKey &);
+bool has_stream_m4(const KernelKey &);
+bool has_stream_m5(const KernelKey &);
+bool has_stream_m6(const KernelKey &);
+bool has_stream_m7(const KernelKey &);
+bool has_stream_m8(const KernelKey &);
+
+bool launch_stream(const KernelKey &k, const SweepArgs &a, hipStream_t s)
+{
+    switch (k.M) {
+    case 1: return launch_stream_m1(k, a, s);
+    case 2: return launch_stream_m2(k, a, s);
+    case 3: return launch_stream_m3(k, a, s);
+    case 4: return launch_stream_m4(k, a, s);
+    case 5: return launch_stream_m5(k, a, s);
+    case 6: return launch_stream_m6(k, a, s);
+    case 7: return launch_stream_m7(k, a, s);
+    case 8: return launch_stream_m8(k, a, s);
+    default: return false;
+    }
+}
+
+bool stream_has(const KernelKey &k)
+{
+    switch (k.M) {
+    case 1: return has_stream_m1(k);
+    case 2: return has_stream_m2(k);
+    case 3: return has_stream_m3(k);
+    case 4: return has_stream_m4(k);
+    case 5: return has_stream_m5(k);
+    case 6: return has_stream_m6(k);
+    case 7: return has_stream_m7(k);
+    case 8: return has_stream_m8(k);
+    default: return false;
+    }
+}
+
+int stream_core_rows(const KernelKey &k) { return k.NW * k.PY - 2 * k.M * (k.T - 1); }
+int stream_core_cols(const KernelKey &k) { return 64 - 2 * k.M * (k.T - 1); }
+
+namespace {
+
+// ------------------------------------------------------------------ status helpers
+struct HipFail {
+    hipError_t e;
+};
+#define FDW_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) throw HipFail{e_};                                           \
+    } while (0)
+
+struct Status {
+    int code;
+};
+
+thread_local fd_options g_last{};
+thread_local bool g_last_valid = false;
+
+// ------------------------------------------------------------------ geometry
+struct Dims {
+    int ndim;
+    int M;
+    int nx, ny, nz;        // as 3-D
+    int64_t N;
+    double h[3];           // spacing of the 3-D axes (1 for absent axes)
+    bool present[3];
+};
+
+int make_dims(const fd_grid *g, Dims &d)
+{
+    if (!g) return FD_EINVAL;
+    if (g->ndim < 1 || g->ndim > 3) return FD_EINVAL;
+    if (g->space_order < 2 || g->space_order > 2 * kMaxM || (g->space_order & 1)) return FD_EINVAL;
+    if (g->reserved != 0) return FD_EINVAL;
+    d.ndim = g->ndim;
+    d.M = g->space_order / 2;
+    int64_t n3[3] = {1, 1, 1};
+    double h3[3] = {1.0, 1.0, 1.0};
+    bool p3[3] = {false, false, false};
+    // 3-D: (x, y, z); 2-D: (x, 1, z); 1-D: (1, 1, z)
+    static const int map[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    for (int a = 0; a < g->ndim; ++a) {
+        if (g->n[a] < 1 || g->n[a] > (1 << 20)) return FD_EINVAL;
+        if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return FD_EINVAL;
+        const int ax = map[g->ndim][a];
+        n3[ax] = g->n[a];
+        h3[ax] = g->h[a];
+        p3[ax] = true;
+    }
+    d.nx = (int)n3[0];
+    d.ny = (int)n3[1];
+    d.nz = (int)n3[2];
+    d.N = n3[0] * n3[1] * n3[2];
+    if (n3[1] * n3[2] >= ((int64_t)1 << 31)) return FD_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        d.h[a] = h3[a];
+        d.present[a] = p3[a];
+    }
+    if (g->sponge < 0) return FD_EINVAL;
+    if (g->sponge > 0) {
+        if (!(g->sponge_vref > 0.0) || !std::isfinite(g->sponge_vref)) return FD_EINVAL;
+        for (int a = 0; a < g->ndim; ++a)
+            if (2 * (int64_t)g->sponge > g->n[a]) return FD_EINVAL;
+    }
+    return FD_OK;
+}
+
+// Map a user index tuple (ndim entries) onto the 3-D (x, y, z) node; -1 if outside.
+int64_t node_of(const Dims &d, const int32_t *idx, int &x, int &y, int &z)
+{
+    int v3[3] = {0, 0, 0};
+    static const int map[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    const int n3[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < d.ndim; ++a) {
+        const int ax = map[d.ndim][a];
+        if (idx[a] < 0 || idx[a] >= n3[ax]) return -1;
+        v3[ax] = idx[a];
+    }
+    x = v3[0];
+    y = v3[1];
+    z = v3[2];
+    return ((int64_t)x * d.ny + y) * d.nz + z;
+}
+
+// Closed-form central second-difference weights of order 2M.
+void fd_weights(int M, double *c)
+{
+    double sum = 0.0;
+    for (int k = 1; k <= M; ++k) {
+        double r = 1.0;
+        for (int j = 1; j <= k; ++j) r *= double(M - k + j) / double(M + j);
+        c[k] = 2.0 * ((k & 1) ? 1.0 : -1.0) * r / (double(k) * k);
+        sum += c[k];
+    }
+    c[0] = -2.0 * sum;
+}
+
+Weights make_weights(const Dims &d)
+{
+    double c[kMaxM + 1];
+    fd_weights(d.M, c);
+    Weights w;
+    std::memset(&w, 0, sizeof w);
+    for (int k = 1; k <= d.M; ++k) {
+        w.wx[k - 1] = d.present[0] ? (float)(c[k] / (d.h[0] * d.h[0])) : 0.0f;
+        w.wy[k - 1] = d.present[1] ? (float)(c[k] / (d.h[1] * d.h[1])) : 0.0f;
+        w.wz[k - 1] = d.present[2] ? (float)(c[k] / (d.h[2] * d.h[2])) : 0.0f;
+    }
+    return w;
+}
+
+// Symbol of the stencil at the Nyquist wavenumber: -c0 - 2 sum_k (-1)^k c_k.
+double nyquist_symbol(int M)
+{
+    double c[kMaxM + 1];
+    fd_weights(M, c);
+    double s = -c[0];
+    for (int k = 1; k <= M; ++k) s -= 2.0 * ((k & 1) ? -1.0 : 1.0) * c[k];
+    return s;
+}
+
+// Sponge profile of one axis divided by 2 dt:  d0 (delta/L)^2 / (2 dt),
+// d0 = 1.5 ln(1000) / (vref L h).
+void sponge_profile(int n, int L, double h, double vref, double dt, bool present, float *out)
+{
+    for (int i = 0; i < n; ++i) {
+        double delta = 0.0;
+        if (present && L > 0) {
+            if (i < L) delta = double(L - i);
+            else if (i > n - 1 - L) delta = double(i - (n - 1 - L));
+        }
+        double d = 0.0;
+        if (delta > 0.0) {
+            const double d0 = 1.5 * std::log(1000.0) / (vref * double(L) * h);
+            const double r = delta / double(L);
+            d = d0 * r * r;
+        }
+        out[i] = (float)(d / (2.0 * dt));
+    }
+}
+
+// ------------------------------------------------------------------ workspace layout
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+constexpr int kStatBlocks = 256;
+
+struct TableBufs {
+    int32_t *xptr, *xe, *yz, *id;
+    float *scale;
+};
+
+struct Layout {
+    float *q = nullptr;
+    float *prof = nullptr;          // px | py | pz
+    float *fields[8] = {};          // spare fields (ping-pong, state)
+    int nfields = 0;
+    TableBufs src{}, rec{};
+    float *vstat = nullptr;
+    double *rpart = nullptr;
+    // gradient
+    float *ckpt = nullptr;          // [nck][2][N]
+    int nck = 0;
+    float *seg = nullptr;           // [K][N] second differences
+    double *g = nullptr;            // [N]
+    float *traces = nullptr;        // [nt][nr]
+    float *resid = nullptr;         // [nt][nr]
+    size_t bytes = 0;
+};
+
+TableBufs carve_table(Carver &cv, int nx, int cnt)
+{
+    TableBufs t;
+    t.xptr = cv.take<int32_t>(nx + 1);
+    t.xe = cv.take<int32_t>(std::max(cnt, 1));
+    t.yz = cv.take<int32_t>(std::max(cnt, 1));
+    t.id = cv.take<int32_t>(std::max(cnt, 1));
+    t.scale = cv.take<float>(std::max(cnt, 1));
+    return t;
+}
+
+int ckpt_interval(const fd_options *o) { return (o && o->ckpt_every > 0) ? o->ckpt_every : 50; }
+
+Layout layout(void *ws, const Dims &d, int64_t nt, int ns, int nr, int op, int nfields,
+              int K)
+{
+    Carver cv(ws);
+    Layout L;
+    L.q = cv.take<float>(d.N);
+    L.prof = cv.take<float>((size_t)d.nx + d.ny + d.nz);
+    L.nfields = nfields;
+    for (int i = 0; i < nfields; ++i) L.fields[i] = cv.take<float>(d.N);
+    L.src = carve_table(cv, d.nx, ns);
+    L.rec = carve_table(cv, d.nx, nr);
+    L.vstat = cv.take<float>(3 * kStatBlocks);
+    L.rpart = cv.take<double>(kStatBlocks);
+    if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
+        L.nck = nt > 0 ? (int)((nt + K - 1) / K) : 0;
+        L.ckpt = cv.take<float>((size_t)std::max(L.nck, 1) * 2 * d.N);
+        L.seg = cv.take<float>((size_t)std::max(1, (int)std::min<int64_t>(K, std::max<int64_t>(nt, 1))) * d.N);
+        L.g = cv.take<double>(d.N);
+        L.traces = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
+        L.resid = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
+    }
+    L.bytes = ((cv.off + 255) & ~(size_t)255) + 256;
+    return L;
+}
+
+// Spare fields each op needs: forward 2 (state if NULL) + 2 (time-block ping-pong);
+// adjoint same; gradient: forward (2 + 2 + 1 scratch) + adjoint (2 + 2).
+int fields_needed(int op)
+{
+    switch (op) {
+    case FD_OP_FORWARD:
+    case FD_OP_ADJOINT: return 4;
+    default: return 9;
+    }
+}
+
+// ------------------------------------------------------------------ planning
+struct Plan {
+    int variant;      // FD_VARIANT_NAIVE / STREAM / TBLOCK
+    KernelKey key;    // for stream / tblock (mode set per use)
+    int lx;
+    bool remap;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, fd_options> g_tune;
+
+std::string tune_key(const Dims &d)
+{
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%d %d %d %d %d gfx950", d.ndim, d.nx, d.ny, d.nz, 2 * d.M);
+    return buf;
+}
+
+void load_tune_file()
+{
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *path = std::getenv("FD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        int nd, nx, ny, nz, so, var, t0, t1, t2, tb;
+        char arch[32];
+        if (std::sscanf(line, "%d %d %d %d %d %31s %d %d %d %d %d", &nd, &nx, &ny, &nz, &so, arch,
+                        &var, &t0, &t1, &t2, &tb) == 11) {
+            char key[128];
+            std::snprintf(key, sizeof key, "%d %d %d %d %d %s", nd, nx, ny, nz, so, arch);
+            fd_options o{};
+            o.variant = var;
+            o.tile[0] = t0;
+            o.tile[1] = t1;
+            o.tile[2] = t2;
+            o.tblock = tb;
+            g_tune[key] = o;
+        }
+    }
+    std::fclose(f);
+}
+
+// Default x-chunk: enough workgroups to fill 256 CUs several times over while
+// keeping the 2 T M warm-up planes small against the chunk.
+int default_lx(const Dims &d, const KernelKey &k)
+{
+    const int ty = stream_core_rows(k), tz = stream_core_cols(k);
+    const int64_t tiles = (int64_t)((d.nz + tz - 1) / tz) * ((d.ny + ty - 1) / ty);
+    const int64_t target = 2048;
+    int64_t ntx = std::max<int64_t>(1, (target + tiles - 1) / tiles);
+    int lx = (int)((d.nx + ntx - 1) / ntx);
+    lx = std::max(lx, 4 * k.T * k.M);
+    return std::min(std::max(lx, 1), d.nx);
+}
+
+KernelKey default_key(const Dims &d, int T)
+{
+    // measured on MI355X: small-PY tiles win for T = 1, a tall (2 rows x 16
+    // waves) tile for T >= 2; fall back to whatever is compiled
+    static const int pref1[][2] = {{4, 4}, {4, 8}, {8, 4}};
+    static const int pref2[][2] = {{2, 16}, {4, 8}, {8, 4}};
+    for (auto &sh : (T == 1 ? pref1 : pref2)) {
+        KernelKey k{d.M, T, sh[0], sh[1], kPlain};
+        if (stream_has(k)) return k;
+    }
+    return KernelKey{d.M, 1, 8, 4, kPlain};
+}
+
+int make_plan(const Dims &d, const fd_options *o, Plan &p)
+{
+    fd_options eff{};
+    if (o) eff = *o;
+    if (eff.reserved != 0) return FD_EINVAL;
+    if (eff.variant == FD_VARIANT_AUTO) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file();
+        auto it = g_tune.find(tune_key(d));
+        if (it != g_tune.end()) {
+            const fd_options &t = it->second;
+            eff.variant = t.variant;
+            for (int i = 0; i < 3; ++i)
+                if (!eff.tile[i]) eff.tile[i] = t.tile[i];
+            if (!eff.tblock) eff.tblock = t.tblock;
+        } else {
+            eff.variant = (d.ndim == 3) ? FD_VARIANT_STREAM : FD_VARIANT_NAIVE;
+        }
+    }
+    p.remap = !(eff.flags & FD_FLAG_NO_XCD_REMAP);
+    p.variant = eff.variant;
+    if (eff.variant == FD_VARIANT_NAIVE) {
+        p.key = KernelKey{d.M, 1, 1, 1, kPlain};
+        p.lx = d.nx;
+        return FD_OK;
+    }
+    if (eff.variant != FD_VARIANT_STREAM && eff.variant != FD_VARIANT_TBLOCK) return FD_EINVAL;
+    int T = 1;
+    if (eff.variant == FD_VARIANT_TBLOCK) T = eff.tblock > 0 ? eff.tblock : 2;
+    if (T < 1 || T > 4) return FD_EINVAL;
+    KernelKey k;
+    if (eff.tile[1] > 0 || eff.tile[2] > 0) {
+        const int PY = eff.tile[2] > 0 ? eff.tile[2] : 8;
+        const int rows = eff.tile[1] > 0 ? eff.tile[1] : 32;
+        if (rows % PY) return FD_EUNSUPPORTED;
+        k = KernelKey{d.M, T, PY, rows / PY, kPlain};
+        if (!stream_has(k)) return FD_EUNSUPPORTED;
+    } else {
+        k = default_key(d, T);
+        if (k.T != T) {
+            if (eff.variant == FD_VARIANT_TBLOCK && eff.tblock > 0) return FD_EUNSUPPORTED;
+        }
+    }
+    p.key = k;
+    p.variant = (k.T >= 2) ? FD_VARIANT_TBLOCK : FD_VARIANT_STREAM;
+    p.lx = eff.tile[0] > 0 ? std::min(eff.tile[0], d.nx) : default_lx(d, k);
+    return FD_OK;
+}
+
+// Key with the same tile for another mode / depth, falling back to T = 1 (8, 4).
+KernelKey key_for(const KernelKey &base, int T, int mode)
+{
+    KernelKey k = base;
+    k.T = T;
+    k.mode = mode;
+    if (stream_has(k)) return k;
+    k = KernelKey{base.M, T, 8, 4, mode};
+    if (stream_has(k)) return k;
+    k = KernelKey{base.M, T, 4, 8, mode};
+    if (stream_has(k)) return k;
+    return KernelKey{base.M, 1, 8, 4, mode};
+}
+
+// ------------------------------------------------------------------ point tables
+struct Entry {
+    int x, y, z, id;
+};
+
+int build_table(const Dims &d, const fd_points *pts, std::vector<Entry> &ent)
+{
+    ent.clear();
+    if (!pts || pts->n == 0) return FD_OK;
+    if (pts->n < 0 || pts->reserved != 0 || !pts->idx) return FD_EINVAL;
+    ent.resize(pts->n);
+    for (int i = 0; i < pts->n; ++i) {
+        int x, y, z;
+        if (node_of(d, pts->idx + (size_t)i * d.ndim, x, y, z) < 0) return FD_EDOM;
+        ent[i] = Entry{x, y, z, i};
+    }
+    std::stable_sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) {
+        if (a.x != b.x) return a.x < b.x;
+        if (a.y != b.y) return a.y < b.y;
+        if (a.z != b.z) return a.z < b.z;
+        return a.id < b.id;
+    });
+    return FD_OK;
+}
+
+// Host staging of a table; kept alive until the copies are enqueued (pageable
+// copies are staged by the runtime before hipMemcpyAsync returns).
+void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs &b,
+                  hipStream_t s)
+{
+    std::vector<int32_t> xptr(d.nx + 1, 0), xe(ent.size()), yz(ent.size()), id(ent.size());
+    for (size_t j = 0; j < ent.size(); ++j) {
+        xptr[ent[j].x + 1]++;
+        xe[j] = ent[j].x;
+        yz[j] = ent[j].y * d.nz + ent[j].z;
+        id[j] = ent[j].id;
+    }
+    for (int x = 0; x < d.nx; ++x) xptr[x + 1] += xptr[x];
+    FDW_HIP(hipMemcpyAsync(b.xptr, xptr.data(), xptr.size() * 4, hipMemcpyHostToDevice, s));
+    if (!ent.empty()) {
+        FDW_HIP(hipMemcpyAsync(b.xe, xe.data(), xe.size() * 4, hipMemcpyHostToDevice, s));
+        FDW_HIP(hipMemcpyAsync(b.yz, yz.data(), yz.size() * 4, hipMemcpyHostToDevice, s));
+        FDW_HIP(hipMemcpyAsync(b.id, id.data(), id.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    FDW_HIP(hipStreamSynchronize(s));
+}
+
+PointTable as_table(const TableBufs &b, int stride, int cnt, bool with_scale)
+{
+    PointTable t;
+    t.xptr = b.xptr;
+    t.xe = b.xe;
+    t.yz = b.yz;
+    t.id = b.id;
+    t.scale = with_scale ? b.scale : nullptr;
+    t.stride = stride;
+    t.cnt = cnt;
+    return t;
+}
+
+// ------------------------------------------------------------------ per-call context
+struct Ctx {
+    Dims d;
+    int64_t nt;
+    double dt;
+    hipStream_t s;
+    Plan plan;
+    Layout L;
+    SweepArgs base;   // common launch arguments
+};
+
+int validate_common(const fd_grid *g, const fd_time *t, const float *v, Dims &d)
+{
+    int rc = make_dims(g, d);
+    if (rc) return rc;
+    if (!t || t->nt < 0 || t->nt > (int64_t)1 << 30 || !(t->dt > 0.0) || !std::isfinite(t->dt))
+        return FD_EINVAL;
+    if (!v) return FD_EINVAL;
+    return FD_OK;
+}
+
+int check_points(const Dims &d, const fd_points *p, bool need_amp, int64_t nt)
+{
+    if (!p) return FD_OK;
+    if (p->n < 0 || p->reserved != 0) return FD_EINVAL;
+    if (p->n > 0 && !p->idx) return FD_EINVAL;
+    if (need_amp && p->n > 0 && nt > 0 && !p->amp) return FD_EINVAL;
+    for (int i = 0; i < p->n; ++i) {
+        int x, y, z;
+        if (node_of(d, p->idx + (size_t)i * d.ndim, x, y, z) < 0) return FD_EDOM;
+    }
+    return FD_OK;
+}
+
+// Prepare q, sponge profiles, weights, point tables and the stability check.
+int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, float inj_alpha,
+            const fd_points *rec, uint32_t flags)
+{
+    const Dims &d = c.d;
+    FDW_HIP(launch_make_q(v, c.L.q, d.N, c.dt * c.dt, c.s));
+    std::vector<float> prof((size_t)d.nx + d.ny + d.nz);
+    sponge_profile(d.nx, g->sponge, d.h[0], g->sponge_vref, c.dt, d.present[0], prof.data());
+    sponge_profile(d.ny, g->sponge, d.h[1], g->sponge_vref, c.dt, d.present[1], prof.data() + d.nx);
+    sponge_profile(d.nz, g->sponge, d.h[2], g->sponge_vref, c.dt, d.present[2],
+                   prof.data() + d.nx + d.ny);
+    FDW_HIP(hipMemcpyAsync(c.L.prof, prof.data(), prof.size() * 4, hipMemcpyHostToDevice, c.s));
+
+    // v statistics: non-finite / non-positive values and the stability limit
+    if (!(flags & FD_FLAG_NO_CFL_CHECK)) {
+        FDW_HIP(launch_vstats(v, d.N, c.L.vstat, kStatBlocks, c.s));
+        std::vector<float> st(3 * kStatBlocks);
+        FDW_HIP(hipMemcpyAsync(st.data(), c.L.vstat, st.size() * 4, hipMemcpyDeviceToHost, c.s));
+        FDW_HIP(hipStreamSynchronize(c.s));
+        float vmax = 0.0f, bad = 0.0f;
+        for (int b = 0; b < kStatBlocks; ++b) {
+            vmax = std::max(vmax, st[3 * b]);
+            bad += st[3 * b + 2];
+        }
+        if (bad > 0.0f) return FD_ENONFINITE;
+        double inv_h2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            if (d.present[a]) inv_h2 += 1.0 / (d.h[a] * d.h[a]);
+        const double lhs = (double)vmax * vmax * c.dt * c.dt * nyquist_symbol(d.M) * inv_h2;
+        if (lhs > 4.0 * (1.0 + 1e-12)) return FD_ECFL;
+    }
+
+    std::vector<Entry> es, er;
+    int rc = build_table(d, inj, es);
+    if (rc) return rc;
+    rc = build_table(d, rec, er);
+    if (rc) return rc;
+    upload_table(d, es, c.L.src, c.s);
+    upload_table(d, er, c.L.rec, c.s);
+
+    SweepArgs &a = c.base;
+    std::memset(&a, 0, sizeof a);
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.sxy = (int64_t)d.ny * d.nz;
+    a.w = make_weights(d);
+    a.q = c.L.q;
+    a.px = c.L.prof;
+    a.py = c.L.prof + d.nx;
+    a.pz = c.L.prof + d.nx + d.ny;
+    a.inj = as_table(c.L.src, inj ? inj->n : 0, (int)es.size(), true);
+    a.rec = as_table(c.L.rec, rec ? rec->n : 0, (int)er.size(), false);
+    a.rscale = 1.0f;
+    a.adir = 1;
+    a.rdir = 1;
+    a.remap = c.plan.remap ? 1 : 0;
+    FDW_HIP(launch_entry_x(a.inj, d.nx, c.L.src.xe, c.s));
+    FDW_HIP(launch_entry_x(a.rec, d.nx, c.L.rec.xe, c.s));
+    FDW_HIP(launch_scales(a, a.inj, c.L.src.scale, inj_alpha, c.s));
+    return FD_OK;
+}
+
+// ------------------------------------------------------------------ the sweep driver
+// State of a running sweep: (cur, prev) plus spare fields for ping-pong.
+struct State {
+    float *cur, *prev;
+    float *spare[3];
+    int nspare;
+};
+
+void swap_in(State &st, float *ncur, float *nprev)
+{
+    // keep every pointer exactly once among cur, prev and spares
+    float *all[5] = {st.cur, st.prev, st.spare[0], st.spare[1], st.spare[2]};
+    const int total = 2 + st.nspare;
+    st.cur = ncur;
+    st.prev = nprev;
+    int k = 0;
+    for (int i = 0; i < total; ++i)
+        if (all[i] != ncur && all[i] != nprev) st.spare[k++] = all[i];
+}
+
+struct StepOpts {
+    int mode = kPlain;       // kPlain / kSaveD2 / kImaging
+    int64_t dslot_first = 0; // d2 slot of the first step in the range
+    int ddir = 1;
+};
+
+// Advance `nsteps` steps, the first one being global step index `step0`.
+void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &so)
+{
+    const Dims &d = c.d;
+    int64_t s = 0;
+    while (s < nsteps) {
+        SweepArgs a = c.base;
+        a.step0 = (int)(step0 + s);
+        a.d2 = c.L.seg;
+        a.dslot0 = so.dslot_first + (int64_t)so.ddir * s;
+        a.ddir = so.ddir;
+        a.g = c.L.g;
+        if (c.plan.variant == FD_VARIANT_NAIVE) {
+            a.u0 = st.cur;
+            a.um = st.prev;
+            float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
+            a.o1 = out;
+            FDW_HIP(launch_naive_step(d.M, a, c.s));
+            FDW_HIP(launch_inject(a, out, a.step0, c.s));
+            FDW_HIP(launch_record(a, out, a.step0, c.s));
+            if (so.mode == kSaveD2)
+                FDW_HIP(launch_save_d2(a, out, st.cur, st.prev, a.d2 + a.dslot0 * d.N, c.s));
+            if (so.mode == kImaging) FDW_HIP(launch_imaging(a, out, a.d2 + a.dslot0 * d.N, a.g, c.s));
+            swap_in(st, out, st.cur);
+            s += 1;
+            continue;
+        }
+        const int T = (nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+        KernelKey k = (T == c.plan.key.T && so.mode == kPlain) ? c.plan.key
+                                                                : key_for(c.plan.key, T, so.mode);
+        if (k.T != T) k = key_for(c.plan.key, 1, so.mode);
+        const int Tk = k.T;
+        a.u0 = st.cur;
+        a.um = st.prev;
+        float *o1, *o2 = nullptr;
+        if (Tk == 1) {
+            o1 = st.prev;  // in place: each point's u^{n-1} is read only by its owner
+        } else {
+            o1 = st.spare[0];
+            o2 = st.spare[1];
+        }
+        a.o1 = o1;
+        a.o2 = o2;
+        a.lx = (k.T == c.plan.key.T && k.PY == c.plan.key.PY && k.NW == c.plan.key.NW)
+                   ? c.plan.lx
+                   : default_lx(d, k);
+        const int ty = stream_core_rows(k), tz = stream_core_cols(k);
+        a.ntz = (d.nz + tz - 1) / tz;
+        a.nty = (d.ny + ty - 1) / ty;
+        a.ntx = (d.nx + a.lx - 1) / a.lx;
+        if (!launch_stream(k, a, c.s)) throw Status{FD_EUNSUPPORTED};
+        FDW_HIP(hipGetLastError());
+        if (Tk == 1) swap_in(st, o1, st.cur);
+        else swap_in(st, o1, o2);
+        s += Tk;
+    }
+}
+
+// Move the final pair (st.cur, st.prev) into the caller's (A, B); tmp is a
+// field distinct from A, B, st.cur and st.prev.
+void place_state(const State &st, float *A, float *B, float *tmp, int64_t N, hipStream_t s)
+{
+    const size_t bytes = (size_t)N * 4;
+    if (st.cur == A && st.prev == B) return;
+    if (st.cur == B && st.prev == A) {
+        FDW_HIP(hipMemcpyAsync(tmp, A, bytes, hipMemcpyDeviceToDevice, s));
+        FDW_HIP(hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, s));
+        FDW_HIP(hipMemcpyAsync(B, tmp, bytes, hipMemcpyDeviceToDevice, s));
+    } else if (st.prev == A) {
+        FDW_HIP(hipMemcpyAsync(B, A, bytes, hipMemcpyDeviceToDevice, s));
+        FDW_HIP(hipMemcpyAsync(A, st.cur, bytes, hipMemcpyDeviceToDevice, s));
+    } else {
+        if (st.cur != A) FDW_HIP(hipMemcpyAsync(A, st.cur, bytes, hipMemcpyDeviceToDevice, s));
+        if (st.prev != B) FDW_HIP(hipMemcpyAsync(B, st.prev, bytes, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+void record_last(const Plan &p)
+{
+    g_last = fd_options{};
+    g_last.variant = p.variant;
+    g_last.tile[0] = p.lx;
+    g_last.tile[1] = p.key.NW * p.key.PY;
+    g_last.tile[2] = p.key.PY;
+    g_last.tblock = p.key.T;
+    g_last_valid = true;
+}
+
+template <class F>
+int guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const HipFail &) {
+        return FD_EHIP;
+    } catch (const Status &st) {
+        return st.code;
+    } catch (const std::bad_alloc &) {
+        return FD_ENOMEM;
+    } catch (...) {
+        return FD_EHIP;
+    }
+}
+
+int check_finite_traces(const float *dev, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return FD_OK;
+    std::vector<float> h(n);
+    FDW_HIP(hipMemcpyAsync(h.data(), dev, n * 4, hipMemcpyDeviceToHost, s));
+    FDW_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(h[i])) return FD_ENONFINITE;
+    return FD_OK;
+}
+
+int ws_check(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws || ws_bytes < need) return FD_EWORKSPACE;
+    if (((uintptr_t)ws) & 255) return FD_EWORKSPACE;
+    return FD_OK;
+}
+
+}  // namespace
+
+}  // namespace fdw
+
+using namespace fdw;
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *fd_strerror(int code)
+{
+    switch (code) {
+    case FD_OK: return "success";
+    case FD_EINVAL: return "invalid argument";
+    case FD_ECFL: return "time step exceeds the leapfrog stability limit";
+    case FD_EDOM: return "source or receiver index outside the grid";
+    case FD_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case FD_ENOMEM: return "host allocation failed";
+    case FD_EHIP: return "HIP runtime error";
+    case FD_ENONFINITE: return "non-finite or non-positive values";
+    case FD_EUNSUPPORTED: return "no compiled kernel for the requested options";
+    default: return "unknown status";
+    }
+}
+
+int fd_version(void) { return 100; }
+
+int fd_last_config(fd_options *out)
+{
+    if (!out || !g_last_valid) return FD_EINVAL;
+    *out = g_last;
+    return FD_OK;
+}
+
+size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_points *src,
+                         const fd_points *rec, const fd_options *opts, int op)
+{
+    Dims d;
+    if (make_dims(grid, d) || !time || time->nt < 0) return 0;
+    if (op < FD_OP_FORWARD || op > FD_OP_VJP) return 0;
+    const int ns = src ? std::max(src->n, 0) : 0;
+    const int nr = rec ? std::max(rec->n, 0) : 0;
+    Layout L = layout(nullptr, d, time->nt, ns, nr, op, fields_needed(op), ckpt_interval(opts));
+    return L.bytes;
+}
+
+int fd_forward(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+               const fd_points *rec, float *rec_out, float *u_state, void *workspace,
+               size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        Ctx c;
+        int rc = validate_common(grid, time, v, c.d);
+        if (rc) return rc;
+        if ((rc = check_points(c.d, src, true, time->nt))) return rc;
+        if ((rc = check_points(c.d, rec, false, time->nt))) return rc;
+        const int nr = rec ? rec->n : 0;
+        if (nr > 0 && time->nt > 0 && !rec_out) return FD_EINVAL;
+        c.nt = time->nt;
+        c.dt = time->dt;
+        c.s = (hipStream_t)stream;
+        if ((rc = make_plan(c.d, opts, c.plan))) return rc;
+        const int ns = src ? src->n : 0;
+        c.L = layout(nullptr, c.d, c.nt, ns, nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
+        c.L = layout(workspace, c.d, c.nt, ns, nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        const uint32_t flags = opts ? opts->flags : 0u;
+        if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
+        c.base.amp = src ? src->amp : nullptr;
+        c.base.rec_out = rec_out;
+        State st;
+        float *A, *B;
+        if (u_state) {
+            A = u_state;
+            B = u_state + c.d.N;
+        } else {
+            A = c.L.fields[2];
+            B = c.L.fields[3];
+            FDW_HIP(launch_zero(A, c.d.N * 4, c.s));
+            FDW_HIP(launch_zero(B, c.d.N * 4, c.s));
+        }
+        st.cur = A;
+        st.prev = B;
+        st.spare[0] = c.L.fields[0];
+        st.spare[1] = c.L.fields[1];
+        st.spare[2] = nullptr;
+        st.nspare = 2;
+        advance(c, st, 0, c.nt, StepOpts{});
+        if (u_state) place_state(st, A, B, c.L.fields[0] == st.cur || c.L.fields[0] == st.prev
+                                               ? c.L.fields[1] : c.L.fields[0], c.d.N, c.s);
+        record_last(c.plan);
+        if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, c.nt * nr, c.s);
+        return FD_OK;
+    });
+}
+
+int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+               const fd_points *rec, float *src_out, float *lam_state, void *workspace,
+               size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        Ctx c;
+        int rc = validate_common(grid, time, v, c.d);
+        if (rc) return rc;
+        if ((rc = check_points(c.d, src, false, time->nt))) return rc;
+        if ((rc = check_points(c.d, rec, true, time->nt))) return rc;
+        const int ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+        if (ns > 0 && time->nt > 0 && !src_out) return FD_EINVAL;
+        c.nt = time->nt;
+        c.dt = time->dt;
+        c.s = (hipStream_t)stream;
+        if ((rc = make_plan(c.d, opts, c.plan))) return rc;
+        c.L = layout(nullptr, c.d, c.nt, nr, ns, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
+        if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
+        c.L = layout(workspace, c.d, c.nt, nr, ns, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
+        const uint32_t flags = opts ? opts->flags : 0u;
+        // receivers inject (scale 1 / (2m + dt damp) = q / (2 dt^2 (1 + eta))), sources record
+        const float alpha = (float)(1.0 / (2.0 * c.dt * c.dt));
+        if ((rc = prepare(c, grid, v, rec, alpha, src, flags))) return rc;
+        c.base.amp = rec ? rec->amp : nullptr;
+        c.base.abase = c.nt - 1;
+        c.base.adir = -1;
+        c.base.rec_out = src_out;
+        c.base.rbase = c.nt - 1;
+        c.base.rdir = -1;
+        c.base.rscale = (float)(2.0 * c.dt * c.dt);
+        State st;
+        st.cur = c.L.fields[2];
+        st.prev = c.L.fields[3];
+        FDW_HIP(launch_zero(st.cur, c.d.N * 4, c.s));
+        FDW_HIP(launch_zero(st.prev, c.d.N * 4, c.s));
+        st.spare[0] = c.L.fields[0];
+        st.spare[1] = c.L.fields[1];
+        st.spare[2] = nullptr;
+        st.nspare = 2;
+        advance(c, st, 0, c.nt, StepOpts{});
+        if (lam_state) {
+            FDW_HIP(hipMemcpyAsync(lam_state, st.cur, c.d.N * 4, hipMemcpyDeviceToDevice, c.s));
+            FDW_HIP(hipMemcpyAsync(lam_state + c.d.N, st.prev, c.d.N * 4, hipMemcpyDeviceToDevice,
+                                   c.s));
+        }
+        record_last(c.plan);
+        if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(src_out, c.nt * ns, c.s);
+        return FD_OK;
+    });
+}
+
+}  // extern "C"
+
+namespace fdw {
+namespace {
+
+// Shared body of fd_gradient / fd_vjp.  y == nullptr: residual d - d_obs
+// (d_obs = rec->amp) and misfit; otherwise y is the trace cotangent.
+int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+                  const fd_points *rec, const float *y, float *grad_v, double *misfit,
+                  float *residual, void *workspace, size_t ws_bytes, const fd_options *opts,
+                  void *stream, int op)
+{
+    Ctx c;
+    int rc = validate_common(grid, time, v, c.d);
+    if (rc) return rc;
+    if ((rc = check_points(c.d, src, true, time->nt))) return rc;
+    if ((rc = check_points(c.d, rec, true, time->nt))) return rc;
+    if (!grad_v) return FD_EINVAL;
+    const int ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+    c.nt = time->nt;
+    c.dt = time->dt;
+    c.s = (hipStream_t)stream;
+    if ((rc = make_plan(c.d, opts, c.plan))) return rc;
+    const int K = ckpt_interval(opts);
+    if (K < 1) return FD_EINVAL;
+    c.L = layout(nullptr, c.d, c.nt, ns, nr, op, fields_needed(op), K);
+    if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
+    c.L = layout(workspace, c.d, c.nt, ns, nr, op, fields_needed(op), K);
+    const uint32_t flags = opts ? opts->flags : 0u;
+    const int64_t N = c.d.N;
+
+    // ---- forward sweep with checkpoints (sources inject, receivers record)
+    if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
+    c.base.amp = src ? src->amp : nullptr;
+    c.base.rec_out = c.L.traces;
+    float *F[5] = {c.L.fields[0], c.L.fields[1], c.L.fields[2], c.L.fields[3], c.L.fields[4]};
+    State st{F[0], F[1], {F[2], F[3], F[4]}, 3};
+    FDW_HIP(launch_zero(st.cur, N * 4, c.s));
+    FDW_HIP(launch_zero(st.prev, N * 4, c.s));
+    for (int j = 0; j < c.L.nck; ++j) {
+        const int64_t k0 = (int64_t)j * K, k1 = std::min<int64_t>(k0 + K, c.nt);
+        float *ck = c.L.ckpt + (size_t)j * 2 * N;
+        FDW_HIP(hipMemcpyAsync(ck, st.cur, N * 4, hipMemcpyDeviceToDevice, c.s));
+        FDW_HIP(hipMemcpyAsync(ck + N, st.prev, N * 4, hipMemcpyDeviceToDevice, c.s));
+        advance(c, st, k0, k1 - k0, StepOpts{});
+    }
+    // ---- residual / cotangent
+    const float *adj_src = y;
+    if (!y) {
+        const int nb = kStatBlocks;
+        float *res = residual ? residual : c.L.resid;
+        FDW_HIP(launch_residual(c.L.traces, rec ? rec->amp : nullptr, res, c.nt * nr, c.L.rpart, nb,
+                                c.s));
+        adj_src = res;
+        if (misfit) {
+            std::vector<double> part(nb);
+            FDW_HIP(hipMemcpyAsync(part.data(), c.L.rpart, nb * 8, hipMemcpyDeviceToHost, c.s));
+            FDW_HIP(hipStreamSynchronize(c.s));
+            double J = 0.0;
+            for (double p : part) J += p;
+            *misfit = J;
+        }
+    }
+    // ---- adjoint sweep with segment recomputation and imaging
+    SweepArgs fwd = c.base;
+    fwd.rec = as_table(c.L.rec, nr, 0, false);  // no recording during recomputation
+    SweepArgs adj = c.base;
+    {
+        // adjoint: receivers inject the residual with scale 1 / (2m + dt damp)
+        // (computed into the receiver table's scale slots); nothing is recorded
+        const float alpha = (float)(1.0 / (2.0 * c.dt * c.dt));
+        FDW_HIP(launch_scales(c.base, as_table(c.L.rec, nr, c.base.rec.cnt, true), c.L.rec.scale,
+                              alpha, c.s));
+        adj.inj = as_table(c.L.rec, nr, c.base.rec.cnt, true);
+        adj.rec = as_table(c.L.src, ns, 0, false);
+        adj.amp = adj_src;
+        adj.abase = c.nt - 1;
+        adj.adir = -1;
+        adj.rec_out = nullptr;
+    }
+    FDW_HIP(launch_zero(c.L.g, N * 8, c.s));
+    float *Aa[4] = {c.L.fields[5], c.L.fields[6], c.L.fields[7], c.L.fields[8]};
+    State sa{Aa[0], Aa[1], {Aa[2], Aa[3], nullptr}, 2};
+    FDW_HIP(launch_zero(sa.cur, N * 4, c.s));
+    FDW_HIP(launch_zero(sa.prev, N * 4, c.s));
+    for (int j = c.L.nck - 1; j >= 0; --j) {
+        const int64_t k0 = (int64_t)j * K, k1 = std::min<int64_t>(k0 + K, c.nt);
+        const float *ck = c.L.ckpt + (size_t)j * 2 * N;
+        State sf{F[0], F[1], {F[2], F[3], F[4]}, 3};
+        FDW_HIP(hipMemcpyAsync(sf.cur, ck, N * 4, hipMemcpyDeviceToDevice, c.s));
+        FDW_HIP(hipMemcpyAsync(sf.prev, ck + N, N * 4, hipMemcpyDeviceToDevice, c.s));
+        c.base = fwd;
+        StepOpts fo;
+        fo.mode = kSaveD2;
+        fo.dslot_first = 0;  // step k0 produces u^{k0+1}: slot (k0+1) - k0 - 1 = 0
+        fo.ddir = 1;
+        advance(c, sf, k0, k1 - k0, fo);
+        c.base = adj;
+        StepOpts ao;
+        ao.mode = kImaging;
+        // adjoint step n produces lambda^{nt-n}; first step here n = nt - k1 -> slot k1 - k0 - 1
+        ao.dslot_first = k1 - k0 - 1;
+        ao.ddir = -1;
+        advance(c, sa, c.nt - k1, k1 - k0, ao);
+    }
+    FDW_HIP(launch_grad_v(c.L.g, v, grad_v, N, c.s));
+    record_last(c.plan);
+    return FD_OK;
+}
+
+}  // namespace
+}  // namespace fdw
+
+extern "C" {
+
+int fd_gradient(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+                const fd_points *rec, float *grad_v, double *misfit, float *residual,
+                void *workspace, size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        return gradient_impl(grid, time, v, src, rec, nullptr, grad_v, misfit, residual, workspace,
+                             ws_bytes, opts, stream, FD_OP_GRADIENT);
+    });
+}
+
+int fd_vjp(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+           const fd_points *rec, float *grad_v, void *workspace, size_t ws_bytes,
+           const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        if (rec && rec->n > 0 && time && time->nt > 0 && !rec->amp) return FD_EINVAL;
+        return gradient_impl(grid, time, v, src, rec, rec ? rec->amp : nullptr, grad_v, nullptr,
+                             nullptr, workspace, ws_bytes, opts, stream, FD_OP_VJP);
+    });
+}
+
+}  // extern "C"
+
+// ====================================================================== autotuner
+namespace fdw {
+namespace {
+
+__global__ void k_fill(float *p, float val, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+struct Candidate {
+    fd_options o;
+};
+
+std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
+{
+    std::vector<Candidate> out;
+    auto push = [&](int variant, int lx, int rows, int py, int tb) {
+        Candidate c;
+        c.o = fixed;
+        c.o.variant = variant;
+        c.o.tile[0] = lx;
+        c.o.tile[1] = rows;
+        c.o.tile[2] = py;
+        c.o.tblock = tb;
+        out.push_back(c);
+    };
+    if (fixed.variant == 0 || fixed.variant == FD_VARIANT_NAIVE) push(FD_VARIANT_NAIVE, 0, 0, 0, 1);
+    static const int shapes[][2] = {{8, 4}, {4, 4}, {16, 2}, {8, 2}, {4, 8}};
+    for (int T = 1; T <= 4; ++T) {
+        const int variant = T == 1 ? FD_VARIANT_STREAM : FD_VARIANT_TBLOCK;
+        if (fixed.variant && fixed.variant != variant) continue;
+        if (fixed.tblock && fixed.tblock != T) continue;
+        for (auto &sh : shapes) {
+            KernelKey k{d.M, T, sh[0], sh[1], kPlain};
+            if (!stream_has(k)) continue;
+            const int lx0 = default_lx(d, k);
+            for (int f : {1, 2}) {
+                const int lx = std::min(d.nx, std::max(4 * T * d.M, lx0 * f));
+                push(variant, lx, sh[0] * sh[1], sh[0], T);
+                if (lx == d.nx) break;
+            }
+        }
+    }
+    return out;
+}
+
+void save_tune(const std::string &key, const fd_options &o)
+{
+    const char *path = std::getenv("FD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.variant, o.tile[0], o.tile[1], o.tile[2],
+                 o.tblock);
+    std::fclose(f);
+}
+
+}  // namespace
+}  // namespace fdw
+
+extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options *inout,
+                           void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&]() -> int {
+        Dims d;
+        int rc = make_dims(grid, d);
+        if (rc) return rc;
+        if (!inout || !time || !(time->dt > 0.0)) return FD_EINVAL;
+        fd_time tt = *time;
+        if (tt.nt < 1) tt.nt = 8;
+        fd_options fixed = *inout;
+        hipStream_t s = (hipStream_t)stream;
+        Layout L0 = layout(nullptr, d, tt.nt, 0, 0, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        if ((rc = ws_check(workspace, ws_bytes, L0.bytes))) return rc;
+        Ctx c;
+        c.d = d;
+        c.nt = tt.nt;
+        c.dt = tt.dt;
+        c.s = s;
+        c.L = layout(workspace, d, tt.nt, 0, 0, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        // a constant medium at 60 % of the stability limit: kernel time does not
+        // depend on the values, only on the sponge branch, which is kept
+        double inv_h2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            if (d.present[a]) inv_h2 += 1.0 / (d.h[a] * d.h[a]);
+        const float qv = (float)(0.36 * 4.0 / (nyquist_symbol(d.M) * inv_h2));
+        hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, s, c.L.q, qv, d.N);
+        FDW_HIP(hipGetLastError());
+        std::vector<float> prof((size_t)d.nx + d.ny + d.nz);
+        sponge_profile(d.nx, grid->sponge, d.h[0], grid->sponge_vref, tt.dt, d.present[0], prof.data());
+        sponge_profile(d.ny, grid->sponge, d.h[1], grid->sponge_vref, tt.dt, d.present[1],
+                       prof.data() + d.nx);
+        sponge_profile(d.nz, grid->sponge, d.h[2], grid->sponge_vref, tt.dt, d.present[2],
+                       prof.data() + d.nx + d.ny);
+        FDW_HIP(hipMemcpyAsync(c.L.prof, prof.data(), prof.size() * 4, hipMemcpyHostToDevice, s));
+        std::vector<Entry> none;
+        upload_table(d, none, c.L.src, s);
+        upload_table(d, none, c.L.rec, s);
+        SweepArgs &a = c.base;
+        std::memset(&a, 0, sizeof a);
+        a.nx = d.nx;
+        a.ny = d.ny;
+        a.nz = d.nz;
+        a.sxy = (int64_t)d.ny * d.nz;
+        a.w = make_weights(d);
+        a.q = c.L.q;
+        a.px = c.L.prof;
+        a.py = c.L.prof + d.nx;
+        a.pz = c.L.prof + d.nx + d.ny;
+        a.inj = as_table(c.L.src, 0, 0, true);
+        a.rec = as_table(c.L.rec, 0, 0, false);
+        a.rscale = 1.0f;
+        a.adir = a.rdir = 1;
+        hipEvent_t e0, e1;
+        FDW_HIP(hipEventCreate(&e0));
+        FDW_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        fd_options best_o = fixed;
+        bool found = false;
+        for (const Candidate &cand : candidates(d, fixed)) {
+            Plan p;
+            if (make_plan(d, &cand.o, p) != FD_OK) continue;
+            c.plan = p;
+            c.base.remap = p.remap ? 1 : 0;
+            State st{c.L.fields[2], c.L.fields[3], {c.L.fields[0], c.L.fields[1], nullptr}, 2};
+            FDW_HIP(launch_zero(st.cur, d.N * 4, s));
+            FDW_HIP(launch_zero(st.prev, d.N * 4, s));
+            const int64_t steps = std::max<int64_t>(tt.nt, p.key.T) / p.key.T * p.key.T;
+            advance(c, st, 0, steps, StepOpts{});  // warm-up
+            FDW_HIP(hipEventRecord(e0, s));
+            advance(c, st, 0, steps, StepOpts{});
+            FDW_HIP(hipEventRecord(e1, s));
+            FDW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            FDW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const float per_step = ms / (float)steps;
+            if (per_step < best) {
+                best = per_step;
+                best_o = cand.o;
+                best_o.variant = p.variant;
+                best_o.tile[0] = p.lx;
+                best_o.tile[1] = p.key.NW * p.key.PY;
+                best_o.tile[2] = p.key.PY;
+                best_o.tblock = p.key.T;
+                found = true;
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (!found) return FD_EUNSUPPORTED;
+        *inout = best_o;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[tune_key(d)] = best_o;
+        }
+        save_tune(tune_key(d), best_o);
+        return FD_OK;
+    });
+}
+
+// ====================================================================== batches
+extern "C" size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int op)
+{
+    if (nshots < 0 || (nshots > 0 && !shots)) return 0;
+    if (op != FD_OP_FORWARD && op != FD_OP_GRADIENT) return 0;
+    size_t total = 0;
+    for (int i = 0; i < nshots; ++i) {
+        const size_t b = fd_workspace_size(&shots[i].grid, &shots[i].time, &shots[i].src,
+                                           &shots[i].rec, &shots[i].opts, op);
+        if (!b) return 0;
+        total += (b + 255) & ~(size_t)255;
+    }
+    return total;
+}
+
+extern "C" int fd_forward_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
+                                uint32_t batch_flags, void *stream)
+{
+    if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
+    const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_FORWARD);
+    if (nshots > 0 && (!workspace || ws_bytes < need)) return FD_EWORKSPACE;
+    (void)batch_flags;
+    size_t off = 0;
+    for (int i = 0; i < nshots; ++i) {
+        fd_shot &sh = shots[i];
+        const size_t b = fd_workspace_size(&sh.grid, &sh.time, &sh.src, &sh.rec, &sh.opts,
+                                           FD_OP_FORWARD);
+        const int rc = fd_forward(&sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, sh.rec_out, nullptr,
+                                  (char *)workspace + off, b, &sh.opts, stream);
+        if (rc) return rc;
+        off += (b + 255) & ~(size_t)255;
+    }
+    return FD_OK;
+}
+
+extern "C" int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
+                                 uint32_t batch_flags, void *stream)
+{
+    if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
+    const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_GRADIENT);
+    if (nshots > 0 && (!workspace || ws_bytes < need)) return FD_EWORKSPACE;
+    (void)batch_flags;
+    size_t off = 0;
+    for (int i = 0; i < nshots; ++i) {
+        fd_shot &sh = shots[i];
+        const size_t b = fd_workspace_size(&sh.grid, &sh.time, &sh.src, &sh.rec, &sh.opts,
+                                           FD_OP_GRADIENT);
+        const int rc = fd_gradient(&sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, sh.grad_v, &sh.misfit,
+                                   nullptr, (char *)workspace + off, b, &sh.opts, stream);
+        if (rc) return rc;
+        off += (b + 255) & ~(size_t)255;
+    }
+    return FD_OK;
+}

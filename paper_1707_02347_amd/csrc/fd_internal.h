@@ -1,0 +1,109 @@
+// fd_internal.h -- structures shared by the HIP kernels and the host planner of
+// libfdwave.so.  Not part of the public ABI (include/fdwave.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+constexpr int kMaxM = 8;  // space order up to 16
+
+// FP32 stencil weights w{x,y,z}[k-1] = c_k / h_a^2 for k = 1..M (zero for an
+// absent axis), computed once on the host in FP64 and rounded to FP32.  The
+// centre weight c_0 = -2 sum_k c_k is not stored: every kernel evaluates
+// sum_k w_k (u(-k) + u(+k) - 2 u_c).
+struct Weights {
+    float wx[kMaxM];
+    float wy[kMaxM];
+    float wz[kMaxM];
+};
+
+// Grid nodes of a point set, bucketed by x (CSR): entries of plane x are
+// [xptr[x], xptr[x+1]), ordered by (y, z, original index).
+struct PointTable {
+    const int32_t *xptr;  // [nx + 1]
+    const int32_t *xe;    // [cnt] x of each entry
+    const int32_t *yz;    // [cnt] y * nz + z
+    const int32_t *id;    // [cnt] original point index (column of amp / record arrays)
+    const float *scale;   // [cnt] injection scale (sources only), else nullptr
+    int32_t stride;       // number of original points (row length of amp / record)
+    int32_t cnt;          // number of entries
+};
+
+// Arguments of one pass of T levels (T = 1 for a plain step).
+struct SweepArgs {
+    int nx, ny, nz;
+    int64_t sxy;      // ny * nz
+    Weights w;
+    const float *q;   // v^2 dt^2
+    const float *px;  // sponge profile / (2 dt) along x, y, z  (damp * v^2 dt / 2 = q * (px + (py + pz)))
+    const float *py;
+    const float *pz;
+    const float *u0;  // u^n
+    const float *um;  // u^{n-1}
+    float *o1;        // receives u^{n+T}   (T = 1: may alias um)
+    float *o2;        // receives u^{n+T-1} (T >= 2)
+    // injection: level t (1..T) produces step s = step0 + t - 1; amplitude row
+    // abase + adir * s.
+    PointTable inj;
+    const float *amp;
+    int64_t abase;
+    int adir;
+    int step0;
+    // recording: row rbase + rdir * s, value scaled by rscale.
+    PointTable rec;
+    float *rec_out;
+    int64_t rbase;
+    int rdir;
+    float rscale;
+    // gradient support: field slot dslot0 + ddir * (t - 1) of d2 (N floats each).
+    float *d2;
+    int64_t dslot0;
+    int ddir;
+    double *g;        // imaging accumulator (FP64, N)
+    // tiling of the launch
+    int lx;           // planes per workgroup along x
+    int ntz, nty, ntx;
+    int remap;        // XCD-aware tile order
+};
+
+enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
+
+// Stream/time-block kernel configuration (compile-time template parameters).
+struct KernelKey {
+    int M, T, PY, NW, mode;
+};
+
+// Launcher for the templated streaming kernel; returns false when no
+// instantiation matches the key.
+bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
+// Tile sizes (core rows / columns) for a key.
+int stream_core_rows(const KernelKey &key);
+int stream_core_cols(const KernelKey &key);
+bool stream_has(const KernelKey &key);
+
+// Naive (untiled) kernels.
+hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s);
+hipError_t launch_inject(const SweepArgs &a, float *field, int step, hipStream_t s);
+hipError_t launch_record(const SweepArgs &a, const float *field, int step, hipStream_t s);
+hipError_t launch_entry_x(const PointTable &t, int nx, int32_t *xe, hipStream_t s);
+hipError_t launch_save_d2(const SweepArgs &a, const float *unew, const float *ucur,
+                          const float *uprev, float *d2, hipStream_t s);
+hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, double *g,
+                          hipStream_t s);
+
+// Preparation / reduction kernels.
+hipError_t launch_make_q(const float *v, float *q, int64_t n, double dt2, hipStream_t s);
+hipError_t launch_vstats(const float *v, int64_t n, float *partial /*[3*nb]*/, int nb,
+                         hipStream_t s);
+hipError_t launch_scales(const SweepArgs &a, const PointTable &t, float *scale, float alpha,
+                         hipStream_t s);
+hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n,
+                           double *partial, int nb, hipStream_t s);
+hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t n,
+                         hipStream_t s);
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t s);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+
+}  // namespace fdw

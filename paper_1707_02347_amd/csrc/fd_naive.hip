@@ -1,0 +1,310 @@
+// fd_naive.hip -- untiled reference kernels and small helper kernels.
+//
+// The untiled step is the plain one-thread-per-point form of the paper's
+// "normal" stencil (Sec. 6.3.1 / Sec. 6.5 transformation types): every
+// neighbour is read from memory.  It fixes the per-point FP32 operation order
+// that every other kernel variant reproduces bit for bit:
+//   lap = 0
+//   for k = 1..M: lap = fma(wx_k, fma(-2, u_c, u(x-k)+u(x+k)), lap)
+//                 lap = fma(wy_k, fma(-2, u_c, u(y-k)+u(y+k)), lap)
+//                 lap = fma(wz_k, fma(-2, u_c, u(z-k)+u(z+k)), lap)
+// (the centre weight c_0 = -2 sum_k c_k is folded into the pairs, so a constant
+// field gives exactly zero and no rounded centre weight biases the sweep)
+//   eta = q * (px[x] + (py[y] + pz[z]))
+//   num = fma(q, lap, fma(eta - 1, u_prev, 2 u_c))
+//   u_new = (eta != 0) ? num / (1 + eta) : num          (IEEE division)
+// then, per source entry at the point in table order: u_new = fma(scale, w, u_new).
+#include "fd_internal.h"
+
+namespace fdw {
+
+template <int M>
+__global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
+{
+    const int z = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int x = blockIdx.z;
+    if (z >= a.nz || y >= a.ny) return;
+    const float *u = a.u0;
+    const int64_t c = (int64_t)x * a.sxy + (int64_t)y * a.nz + z;
+    const float uc = u[c];
+    float lap = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= M; ++k) {
+        const float xm = (x - k >= 0) ? u[c - k * a.sxy] : 0.0f;
+        const float xp = (x + k < a.nx) ? u[c + k * a.sxy] : 0.0f;
+        const float ym = (y - k >= 0) ? u[c - (int64_t)k * a.nz] : 0.0f;
+        const float yp = (y + k < a.ny) ? u[c + (int64_t)k * a.nz] : 0.0f;
+        const float zm = (z - k >= 0) ? u[c - k] : 0.0f;
+        const float zp = (z + k < a.nz) ? u[c + k] : 0.0f;
+        lap = fmaf(a.w.wx[k - 1], fmaf(-2.0f, uc, xm + xp), lap);
+        lap = fmaf(a.w.wy[k - 1], fmaf(-2.0f, uc, ym + yp), lap);
+        lap = fmaf(a.w.wz[k - 1], fmaf(-2.0f, uc, zm + zp), lap);
+    }
+    const float qv = a.q[c];
+    const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
+    const float num = fmaf(qv, lap, fmaf(eta - 1.0f, a.um[c], 2.0f * uc));
+    float up = num;
+    if (eta != 0.0f) up = num / (1.0f + eta);
+    a.o1[c] = up;
+}
+
+hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s)
+{
+    dim3 block(64, 4, 1);
+    dim3 grid((a.nz + 63) / 64, (a.ny + 3) / 4, a.nx);
+    switch (M) {
+    case 1: hipLaunchKernelGGL(k_naive_step<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_naive_step<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_naive_step<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_naive_step<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_naive_step<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_naive_step<6>, grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL(k_naive_step<7>, grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_naive_step<8>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// One thread per table entry; the first entry of each run of equal grid nodes
+// applies the whole run in table order, so repeated points are deterministic.
+__global__ void k_inject(PointTable t, int64_t sxy, const float *amp, int64_t row, float *field)
+{
+    const int32_t *xe = t.xe;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= t.cnt) return;
+    if (j > 0 && xe[j - 1] == xe[j] && t.yz[j - 1] == t.yz[j]) return;
+    const int64_t p = (int64_t)xe[j] * sxy + t.yz[j];
+    float val = field[p];
+    for (int k = j; k < t.cnt && xe[k] == xe[j] && t.yz[k] == t.yz[j]; ++k)
+        val = fmaf(t.scale[k], amp[row * t.stride + t.id[k]], val);
+    field[p] = val;
+}
+
+__global__ void k_record(PointTable t, int64_t sxy, const float *field, float *out, int64_t row,
+                         float rscale)
+{
+    const int32_t *xe = t.xe;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= t.cnt) return;
+    const int64_t p = (int64_t)xe[j] * sxy + t.yz[j];
+    out[row * t.stride + t.id[j]] = field[p] * rscale;
+}
+
+// The x coordinate of every entry is recovered from the CSR row pointers.
+__global__ void k_entry_x(const int32_t *xptr, int nx, int32_t *xe)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    for (int j = xptr[x]; j < xptr[x + 1]; ++j) xe[j] = x;
+}
+
+hipError_t launch_entry_x(const PointTable &t, int nx, int32_t *xe, hipStream_t s)
+{
+    if (t.cnt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_x, dim3((nx + 255) / 256), dim3(256), 0, s, t.xptr, nx, xe);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject(const SweepArgs &a, float *field, int step, hipStream_t s)
+{
+    if (a.inj.cnt == 0) return hipSuccess;
+    const int64_t row = a.abase + (int64_t)a.adir * step;
+    hipLaunchKernelGGL(k_inject, dim3((a.inj.cnt + 63) / 64), dim3(64), 0, s, a.inj, a.sxy, a.amp,
+                       row, field);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const SweepArgs &a, const float *field, int step, hipStream_t s)
+{
+    if (a.rec.cnt == 0) return hipSuccess;
+    const int64_t row = a.rbase + (int64_t)a.rdir * step;
+    hipLaunchKernelGGL(k_record, dim3((a.rec.cnt + 63) / 64), dim3(64), 0, s, a.rec, a.sxy, field,
+                       a.rec_out, row, a.rscale);
+    return hipGetLastError();
+}
+
+__global__ void k_save_d2(const float *unew, const float *ucur, const float *uprev, float *d2,
+                          int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d2[i] = fmaf(-2.0f, ucur[i], unew[i]) + uprev[i];
+}
+
+hipError_t launch_save_d2(const SweepArgs &a, const float *unew, const float *ucur,
+                          const float *uprev, float *d2, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.nx * a.sxy;
+    hipLaunchKernelGGL(k_save_d2, dim3(4096), dim3(256), 0, s, unew, ucur, uprev, d2, n);
+    return hipGetLastError();
+}
+
+__global__ void k_imaging(const float *lam, const float *d2, double *g, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = fma((double)lam[i], (double)d2[i], g[i]);
+}
+
+hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, double *g,
+                          hipStream_t s)
+{
+    const int64_t n = (int64_t)a.nx * a.sxy;
+    hipLaunchKernelGGL(k_imaging, dim3(4096), dim3(256), 0, s, lam, d2, g, n);
+    return hipGetLastError();
+}
+
+__global__ void k_make_q(const float *v, float *q, int64_t n, double dt2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double vv = (double)v[i];
+        q[i] = (float)(vv * vv * dt2);
+    }
+}
+
+hipError_t launch_make_q(const float *v, float *q, int64_t n, double dt2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_make_q, dim3(4096), dim3(256), 0, s, v, q, n, dt2);
+    return hipGetLastError();
+}
+
+// Per-block (max v, min v, count of non-finite or non-positive v).
+__global__ __launch_bounds__(256) void k_vstats(const float *v, int64_t n, float *partial)
+{
+    __shared__ float smax[256], smin[256], sbad[256];
+    float mx = 0.0f, mn = 3.0e38f, bad = 0.0f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = v[i];
+        if (!(x > 0.0f) || !(x < 3.0e38f)) bad += 1.0f;
+        else {
+            mx = fmaxf(mx, x);
+            mn = fminf(mn, x);
+        }
+    }
+    smax[threadIdx.x] = mx;
+    smin[threadIdx.x] = mn;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + o]);
+            smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + o]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x + 0] = smax[0];
+        partial[3 * blockIdx.x + 1] = smin[0];
+        partial[3 * blockIdx.x + 2] = sbad[0];
+    }
+}
+
+hipError_t launch_vstats(const float *v, int64_t n, float *partial, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vstats, dim3(nb), dim3(256), 0, s, v, n, partial);
+    return hipGetLastError();
+}
+
+// Injection scale alpha * q / (1 + eta) at each entry's node (same eta as the update).
+__global__ void k_scales(SweepArgs a, PointTable t, float *scale, float alpha)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= t.cnt) return;
+    const int x = t.xe[j];
+    const int y = t.yz[j] / a.nz;
+    const int z = t.yz[j] - y * a.nz;
+    const float qv = a.q[(int64_t)x * a.sxy + t.yz[j]];
+    const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
+    float base = qv;
+    if (eta != 0.0f) base = qv / (1.0f + eta);
+    scale[j] = alpha * base;
+}
+
+hipError_t launch_scales(const SweepArgs &a, const PointTable &t, float *scale, float alpha,
+                         hipStream_t s)
+{
+    if (t.cnt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scales, dim3((t.cnt + 63) / 64), dim3(64), 0, s, a, t, scale, alpha);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_residual(const float *d, const float *dobs, float *res,
+                                                  int64_t n, double *partial)
+{
+    __shared__ double sj[256];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double r = (double)d[i] - (double)dobs[i];
+        res[i] = (float)r;
+        acc += 0.5 * r * r;
+    }
+    sj[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sj[threadIdx.x] += sj[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sj[0];
+}
+
+hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n,
+                           double *partial, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, s, d, dobs, res, n, partial);
+    return hipGetLastError();
+}
+
+// grad_v = dJ/dm * (-2 / v^3) with dJ/dm = -2 g  ->  4 g / v^3, evaluated in FP64.
+__global__ void k_grad_v(const double *g, const float *v, float *gv, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double vv = (double)v[i];
+        gv[i] = (float)(4.0 * g[i] / (vv * vv * vv));
+    }
+}
+
+hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t n,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_v, dim3(4096), dim3(256), 0, s, g, v, grad_v, n);
+    return hipGetLastError();
+}
+
+// Plain fill kernel (also safe inside captured graphs, unlike memset nodes).
+__global__ void k_zero(uint32_t *p, int64_t nwords)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t s)
+{
+    if (bytes <= 0) return hipSuccess;
+    if (bytes % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (uint32_t *)p, bytes / 4);
+    return hipGetLastError();
+}
+
+__global__ void k_copy(float *dst, const float *src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace fdw
