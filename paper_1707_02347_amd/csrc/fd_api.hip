@@ -123,7 +123,9 @@ int make_dims(const fd_grid *g, Dims &d)
     d.ny = (int)n3[1];
     d.nz = (int)n3[2];
     d.N = n3[0] * n3[1] * n3[2];
-    if (n3[1] * n3[2] >= ((int64_t)1 << 31)) return FD_EINVAL;
+    // one (y, z) plane must stay below 2^29 points: kernels address a plane
+    // with 32-bit byte offsets and mark points outside the grid with offset 2^31
+    if (n3[1] * n3[2] >= ((int64_t)1 << 29)) return FD_EINVAL;
     for (int a = 0; a < 3; ++a) {
         d.h[a] = h3[a];
         d.present[a] = p3[a];
@@ -178,6 +180,21 @@ Weights make_weights(const Dims &d)
         w.wy[k - 1] = d.present[1] ? (float)(c[k] / (d.h[1] * d.h[1])) : 0.0f;
         w.wz[k - 1] = d.present[2] ? (float)(c[k] / (d.h[2] * d.h[2])) : 0.0f;
     }
+    // isotropic: every present axis has bit-identical weights; the kernels then
+    // read the common weight from wx, so wx must hold it even if x is absent
+    int npresent = 0;
+    bool iso = true;
+    const float *ref = nullptr;
+    const float *ws[3] = {w.wx, w.wy, w.wz};
+    for (int a = 0; a < 3; ++a) {
+        if (!d.present[a]) continue;
+        ++npresent;
+        if (!ref) ref = ws[a];
+        else if (std::memcmp(ref, ws[a], sizeof(float) * kMaxM) != 0) iso = false;
+    }
+    w.iso = iso ? 1 : 0;
+    w.cc = -2.0f * (float)npresent;
+    if (iso && ref != w.wx) std::memcpy(w.wx, ref, sizeof(float) * kMaxM);
     return w;
 }
 
@@ -357,7 +374,7 @@ int default_lx(const Dims &d, const KernelKey &k)
     int64_t ntx = std::max<int64_t>(1, (target + tiles - 1) / tiles);
     int lx = (int)((d.nx + ntx - 1) / ntx);
     lx = std::max(lx, 4 * k.T * k.M);
-    return std::min(std::max(lx, 1), d.nx);
+    return std::min(std::min(std::max(lx, 1), d.nx), kMaxLx);
 }
 
 KernelKey default_key(const Dims &d, int T)
@@ -418,7 +435,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
     }
     p.key = k;
     p.variant = (k.T >= 2) ? FD_VARIANT_TBLOCK : FD_VARIANT_STREAM;
-    p.lx = eff.tile[0] > 0 ? std::min(eff.tile[0], d.nx) : default_lx(d, k);
+    p.lx = eff.tile[0] > 0 ? std::min(std::min(eff.tile[0], d.nx), kMaxLx) : default_lx(d, k);
     return FD_OK;
 }
 

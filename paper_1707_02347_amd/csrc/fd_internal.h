@@ -7,16 +7,23 @@
 
 namespace fdw {
 
-constexpr int kMaxM = 8;  // space order up to 16
+constexpr int kMaxM = 8;     // space order up to 16
+constexpr int kMaxLx = 512;  // planes per workgroup chunk (per-plane tables live in LDS)
 
 // FP32 stencil weights w{x,y,z}[k-1] = c_k / h_a^2 for k = 1..M (zero for an
 // absent axis), computed once on the host in FP64 and rounded to FP32.  The
 // centre weight c_0 = -2 sum_k c_k is not stored: every kernel evaluates
 // sum_k w_k (u(-k) + u(+k) - 2 u_c).
+// When every present axis has the same weights ("isotropic"), kernels use the
+// cheaper, equally cancellation-free form
+//   lap = sum_k w_k ((sx + sy) + sz - 2 d u_c)      (cc = -2 d, d present axes)
+// with s_a = u(-k e_a) + u(+k e_a); otherwise sum_k sum_a w_{a,k} (s_a - 2 u_c).
 struct Weights {
     float wx[kMaxM];
     float wy[kMaxM];
     float wz[kMaxM];
+    float cc;
+    int iso;
 };
 
 // Grid nodes of a point set, bucketed by x (CSR): entries of plane x are
@@ -84,7 +91,7 @@ int stream_core_cols(const KernelKey &key);
 bool stream_has(const KernelKey &key);
 
 // Naive (untiled) kernels.
-hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s);
+hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s);  // form from a.w.iso
 hipError_t launch_inject(const SweepArgs &a, float *field, int step, hipStream_t s);
 hipError_t launch_record(const SweepArgs &a, const float *field, int step, hipStream_t s);
 hipError_t launch_entry_x(const PointTable &t, int nx, int32_t *xe, hipStream_t s);

@@ -9,7 +9,10 @@
 //                 lap = fma(wy_k, fma(-2, u_c, u(y-k)+u(y+k)), lap)
 //                 lap = fma(wz_k, fma(-2, u_c, u(z-k)+u(z+k)), lap)
 // (the centre weight c_0 = -2 sum_k c_k is folded into the pairs, so a constant
-// field gives exactly zero and no rounded centre weight biases the sweep)
+// field gives exactly zero and no rounded centre weight biases the sweep);
+// on isotropic grids (all present axes share their FP32 weights) the form is
+//   for k = 1..M: lap = fma(w_k, fma(cc, u_c, ((sx + sy) + sz)), lap),  cc = -2 d,
+// with s_a = u(-k e_a) + u(+k e_a) (an absent axis contributes +0).
 //   eta = q * (px[x] + (py[y] + pz[z]))
 //   num = fma(q, lap, fma(eta - 1, u_prev, 2 u_c))
 //   u_new = (eta != 0) ? num / (1 + eta) : num          (IEEE division)
@@ -18,7 +21,7 @@
 
 namespace fdw {
 
-template <int M>
+template <int M, bool ISO>
 __global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
 {
     const int z = blockIdx.x * 64 + threadIdx.x;
@@ -37,9 +40,14 @@ __global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
         const float yp = (y + k < a.ny) ? u[c + (int64_t)k * a.nz] : 0.0f;
         const float zm = (z - k >= 0) ? u[c - k] : 0.0f;
         const float zp = (z + k < a.nz) ? u[c + k] : 0.0f;
-        lap = fmaf(a.w.wx[k - 1], fmaf(-2.0f, uc, xm + xp), lap);
-        lap = fmaf(a.w.wy[k - 1], fmaf(-2.0f, uc, ym + yp), lap);
-        lap = fmaf(a.w.wz[k - 1], fmaf(-2.0f, uc, zm + zp), lap);
+        if constexpr (ISO) {
+            const float s = ((xm + xp) + (ym + yp)) + (zm + zp);
+            lap = fmaf(a.w.wx[k - 1], fmaf(a.w.cc, uc, s), lap);
+        } else {
+            lap = fmaf(a.w.wx[k - 1], fmaf(-2.0f, uc, xm + xp), lap);
+            lap = fmaf(a.w.wy[k - 1], fmaf(-2.0f, uc, ym + yp), lap);
+            lap = fmaf(a.w.wz[k - 1], fmaf(-2.0f, uc, zm + zp), lap);
+        }
     }
     const float qv = a.q[c];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
@@ -53,17 +61,23 @@ hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s)
 {
     dim3 block(64, 4, 1);
     dim3 grid((a.nz + 63) / 64, (a.ny + 3) / 4, a.nx);
+#define FDW_NAIVE(MM)                                                                      \
+    case MM:                                                                               \
+        if (a.w.iso) hipLaunchKernelGGL((k_naive_step<MM, true>), grid, block, 0, s, a);     \
+        else hipLaunchKernelGGL((k_naive_step<MM, false>), grid, block, 0, s, a);            \
+        break;
     switch (M) {
-    case 1: hipLaunchKernelGGL(k_naive_step<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_naive_step<2>, grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_naive_step<3>, grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_naive_step<4>, grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL(k_naive_step<5>, grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_naive_step<6>, grid, block, 0, s, a); break;
-    case 7: hipLaunchKernelGGL(k_naive_step<7>, grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_naive_step<8>, grid, block, 0, s, a); break;
+        FDW_NAIVE(1)
+        FDW_NAIVE(2)
+        FDW_NAIVE(3)
+        FDW_NAIVE(4)
+        FDW_NAIVE(5)
+        FDW_NAIVE(6)
+        FDW_NAIVE(7)
+        FDW_NAIVE(8)
     default: return hipErrorInvalidValue;
     }
+#undef FDW_NAIVE
     return hipGetLastError();
 }
 

@@ -18,6 +18,15 @@
 // bounded by the modulo buffer (Sec. 6.3.2); on the GPU the time tile lives in
 // registers and LDS instead of a modulo-indexed array.
 //
+// Memory access: every global load of an iteration is issued one plane ahead
+// as a raw buffer load: the buffer resource covers exactly one plane of one
+// field (record count 0 for a plane outside the grid or not needed), and the
+// per-lane byte offset of a point outside the grid is 0x80000000, beyond any
+// plane.  Out-of-range buffer loads return 0 on CDNA, so the Dirichlet zeros
+// come from the hardware range check: no load sits behind a branch or a
+// select, and no wait on a late load drains the prefetch.  Per-plane scalars
+// (sponge profile, point table ranges) are staged in LDS once per workgroup.
+//
 // The per-point FP32 operation order is the one fixed by the untiled kernel
 // (fd_naive.hip), so every configuration returns bit-identical results.
 #pragma once
@@ -41,20 +50,88 @@ struct Geo {
     static constexpr int NHALO = 2 * M * L0W + RY * 2 * M;
     static constexpr int HS = (NHALO + NT - 1) / NT;
     static constexpr int AQ = (T - 1) * M + 1;   // imaging accumulator queue length
+    static constexpr int SPAN = kMaxLx + 2 * (T - 1) * M + 2;  // per-plane table entries
     static_assert(TY >= 1 && TZ >= 1, "core tile must be non-empty");
 };
 
-template <int M, int T, int PY, int NW, int MODE>
+__device__ __forceinline__ float ld(const float *base, uint32_t byte_off)
+{
+    return *(const float *)((const char *)base + byte_off);
+}
+
+constexpr uint32_t kOutside = 0x80000000u;  // byte offset of a point outside the grid
+
+// Buffer resource over plane `plane` of a field (an empty range if !valid).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field, int plane,
+                                                             int64_t sxy, bool valid)
+{
+    const float *base = field + (int64_t)(valid ? plane : 0) * sxy;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0,
+                                             valid ? (int)(uint32_t)(sxy * 4) : 0, 0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
+__device__ __forceinline__ float *at(float *base, uint32_t byte_off)
+{
+    return (float *)((char *)base + byte_off);
+}
+
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
 struct StreamKernel {
     using G = Geo<M, T, PY, NW>;
+    // Register queues along x: for short queues the x loop is unrolled by the
+    // queue length Q and the queues rotate by renaming (slot of logical entry j
+    // at phase PH is (PH + 1 + j) mod Q); long queues (M > 4) shift instead, to
+    // keep the loop body small enough for the instruction cache.
+    static constexpr int Q = G::Q;
+    static constexpr bool ROT = (Q <= 9);
+    static constexpr int UNROLL = ROT ? Q : 1;
+    // prefetch depth in planes: two for short stencils; one for M > 4, where the
+    // extra registers would cost a wave per SIMD
+    static constexpr int PD = (M <= 4) ? 2 : 1;
+    // slot of logical queue entry j at phase PH, after / before this phase's push
+    template <int PH>
+    __device__ static constexpr int pj(int j)
+    {
+        return ROT ? (PH + 1 + j) % Q : j;
+    }
+    template <int PH>
+    __device__ static constexpr int pjb(int j)
+    {
+        return ROT ? (PH + j) % Q : j;
+    }
 
     // Level-0 plane with its M-wide halo ring; planes of levels 1..T-1 over the
     // owned region, padded by M rows above and below so that the rows a thread
     // reads next to its own (used only where they lie inside the level's
-    // region) always stay inside the buffer.
+    // region) always stay inside the buffer; per-plane tables of the chunk.
     struct Smem {
         float s0[2][G::L0H * G::L0W];
         float s1[(T > 1) ? (T - 1) : 1][2][(T > 1) ? (G::RY + 2 * M) * G::RZ : 1];
+        float px[G::SPAN];
+        int ixp[G::SPAN];
+        int rxp[G::SPAN];
+    };
+
+    struct Pre {
+        float head[PY];
+        float halo[G::HS];
+        float up1[PY];
+        float q[T][PY];
+    };
+
+    struct Thread {
+        int lane, wv, x0, xend, cbase;
+        uint32_t bo[PY];    // byte offset of each owned point in a plane (kOutside if outside)
+        bool din[PY];       // owned point inside the grid
+        bool core[PY];      // owned point inside the output tile
+        float pyz[PY];      // py[y] + pz[z]
+        uint32_t hb[G::HS]; // byte offsets of this thread's halo slots (kOutside if outside)
+        bool hv[G::HS];     // halo slot inside the grid
     };
 
     __device__ static void run(const SweepArgs &a, Smem &sm)
@@ -72,53 +149,46 @@ struct StreamKernel {
         const int bx = rest / a.nty;
         const int z1 = bz * G::TZ - G::H1;
         const int y1 = by * G::TY - G::H1;
-        const int x0 = bx * a.lx;
-        const int xend = min(x0 + a.lx, a.nx);
 
-        const int lane = threadIdx.x & 63;
-        const int wv = threadIdx.x >> 6;
-        const int z = z1 + lane;
+        Thread th;
+        th.x0 = bx * a.lx;
+        th.xend = min(th.x0 + a.lx, a.nx);
+        th.cbase = th.x0 - (T - 1) * M;
+        th.lane = threadIdx.x & 63;
+        th.wv = threadIdx.x >> 6;
+        const int z = z1 + th.lane;
         const bool zin = (unsigned)z < (unsigned)a.nz;
         const float pzv = zin ? a.pz[z] : 0.0f;
-
-        int32_t yz[PY];
-        bool din[PY];      // point inside the grid (y and z)
-        float pyz[PY];     // py[y] + pz[z]
-        bool core[PY];     // inside the output tile (and the grid)
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
-            const int rr = wv * PY + r;
+            const int rr = th.wv * PY + r;
             const int y = y1 + rr;
             const bool yin = (unsigned)y < (unsigned)a.ny;
-            din[r] = yin && zin;
-            yz[r] = y * a.nz + z;
-            pyz[r] = din[r] ? (a.py[y] + pzv) : 0.0f;
-            core[r] = din[r] && rr >= G::H1 && rr < G::RY - G::H1 && lane >= G::H1 &&
-                      lane < G::RZ - G::H1;
+            th.din[r] = yin && zin;
+            th.bo[r] = th.din[r] ? (uint32_t)(y * a.nz + z) * 4u : kOutside;
+            th.pyz[r] = th.din[r] ? (a.py[y] + pzv) : 0.0f;
+            th.core[r] = th.din[r] && rr >= G::H1 && rr < G::RY - G::H1 && th.lane >= G::H1 &&
+                         th.lane < G::RZ - G::H1;
         }
-
-        // -------- halo ring of the level-0 plane (positions fixed for the whole pass)
-        int32_t hg[G::HS];  // in-plane global offset, -1 if outside the grid or unused
+        // halo ring of the level-0 plane (positions fixed for the whole pass)
 #pragma unroll
         for (int s = 0; s < G::HS; ++s) {
-            const int h = threadIdx.x + s * G::NT;
-            int row = 0, col = 0;
-            bool used = h < G::NHALO;
-            if (h < 2 * M * G::L0W) {
-                const int band = h / G::L0W;
-                col = h - band * G::L0W;
-                row = band < M ? band : band + G::RY;
-            } else {
-                const int h2 = h - 2 * M * G::L0W;
-                row = M + h2 / (2 * M);
-                const int cj = h2 % (2 * M);
-                col = cj < M ? cj : cj + G::RZ;
-            }
+            int row, col;
+            const bool used = halo_pos(threadIdx.x + s * G::NT, row, col);
             const int gy = y1 - M + row, gz = z1 - M + col;
-            hg[s] = (used && (unsigned)gy < (unsigned)a.ny && (unsigned)gz < (unsigned)a.nz)
-                        ? gy * a.nz + gz
-                        : -1;
+            th.hv[s] = used && (unsigned)gy < (unsigned)a.ny && (unsigned)gz < (unsigned)a.nz;
+            th.hb[s] = th.hv[s] ? (uint32_t)(gy * a.nz + gz) * 4u : kOutside;
         }
+        // per-plane tables of the planes any level of this chunk computes
+        const int span = th.xend - th.x0 + 2 * (T - 1) * M + 1;
+        for (int j = threadIdx.x; j < span; j += G::NT) {
+            const int c = th.cbase + j;
+            const bool cin = (unsigned)c < (unsigned)a.nx;
+            sm.px[j] = cin ? a.px[c] : 0.0f;
+            sm.ixp[j] = (a.inj.cnt > 0 && c >= 0 && c <= a.nx) ? a.inj.xptr[c] : 0;
+            sm.rxp[j] = (a.rec.cnt > 0 && c >= 0 && c <= a.nx) ? a.rec.xptr[c] : 0;
+        }
+        // (the first barrier of the loop orders these writes before any read)
 
         float qu[T][PY][G::Q];  // level t's queue of u^{t-1}: planes c_t - M .. c_t + M
 #pragma unroll
@@ -136,130 +206,159 @@ struct StreamKernel {
                 for (int j = 0; j < G::AQ; ++j) acc[r][j] = 0.0;
         }
 
-        const int ibeg = x0 - T * M;
-        const int iend = xend + T * M;
+        const int ibeg = th.x0 - T * M;
+        const int iend = th.xend + T * M;
         const int64_t N = (int64_t)a.nx * a.sxy;
 
-        // Every global load of an iteration is issued one iteration ahead: the
-        // head plane i of u^n, the level-0 halo ring and u^{n-1} at plane i - M,
-        // and q at each level's plane i - t M.  A load is skipped (value 0) when
-        // its plane is outside the grid or outside the planes the level needs.
-        Pre nx_;
-        load(a, nx_, ibeg, x0, xend, yz, din, hg);
-        for (int i = ibeg; i < iend; ++i) {
-            const int par = i & 1;
-            Pre cur = nx_;
-            if (i + 1 < iend) load(a, nx_, i + 1, x0, xend, yz, din, hg);
-            if constexpr (MODE == kImaging) {
+        Pre pf[PD];  // pf[d] holds the loads of iteration i + d
 #pragma unroll
-                for (int r = 0; r < PY; ++r)
+        for (int d = 0; d < PD; ++d) load(a, th, pf[d], ibeg + d);
+        for (int i0 = ibeg; i0 < iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, iend, N);
+    }
+
+    // Iterations i0 + PH .. i0 + UNROLL - 1 of the x loop (one per phase).  Each
+    // iteration publishes the y/z planes of all T levels first (level t needs
+    // u^{t-1} at plane c_t, which entered its queue M iterations ago), so one
+    // barrier per iteration serves every level.
+    template <int PH, class QU, class ACC>
+    __device__ static __forceinline__ void block(const SweepArgs &a, Smem &sm, const Thread &th,
+                                                 QU &qu, ACC &acc, Pre (&pf)[PD], int i0, int iend,
+                                                 int64_t N)
+    {
+        if constexpr (PH < UNROLL) {
+            const int i = i0 + PH;
+            if (i < iend) {
+                const int par = i & 1;
+                const Pre cur = pf[0];
 #pragma unroll
-                    for (int j = 0; j + 1 < G::AQ; ++j) acc[r][j] = acc[r][j + 1];
+                for (int d = 0; d + 1 < PD; ++d) pf[d] = pf[d + 1];
+                if (i + PD < iend) load(a, th, pf[PD - 1], i + PD);
+                if constexpr (MODE == kImaging) {
+#pragma unroll
+                    for (int r = 0; r < PY; ++r)
+#pragma unroll
+                        for (int j = 0; j + 1 < G::AQ; ++j) acc[r][j] = acc[r][j + 1];
+                }
+                publish<1, PH>(sm, th, qu, cur, par);
+                __syncthreads();
+                float val[PY];  // value produced by the previous level in this iteration
+#pragma unroll
+                for (int r = 0; r < PY; ++r) val[r] = cur.head[r];
+                level<1, PH>(a, sm, th, qu, acc, val, cur, i, par, N);
+                block<PH + 1>(a, sm, th, qu, acc, pf, i0, iend, N);
             }
-            float val[PY];  // value produced by the previous level in this iteration
-#pragma unroll
-            for (int r = 0; r < PY; ++r) val[r] = cur.head[r];
-            level<1>(a, sm, qu, acc, val, cur, i, par, x0, xend, N, lane, wv, yz, din, pyz, core);
         }
     }
 
-    struct Pre {
-        float head[PY];
-        float halo[G::HS];
-        float up1[PY];
-        float q[T][PY];
-    };
-
-    // Planes level t must produce: [x0 - (T - t) M, xend + (T - t) M) within the grid.
-    __device__ static __forceinline__ bool needed(const SweepArgs &a, int t, int c, int x0, int xend)
+    // Write the centre plane c_t of u^{t-1} (queue entry M after this phase's
+    // push, M + 1 before it) into level t's LDS plane; level 1 adds the halo ring.
+    template <int t, int PH, class QU>
+    __device__ static __forceinline__ void publish(Smem &sm, const Thread &th, QU &qu, const Pre &P,
+                                                   int par)
     {
-        return (unsigned)c < (unsigned)a.nx && c >= x0 - (T - t) * M && c < xend + (T - t) * M;
+        if constexpr (t <= T) {
+            constexpr int W = (t == 1) ? G::L0W : G::RZ;
+            constexpr int COFF = (t == 1) ? M : 0;
+            float *S;
+            if constexpr (t == 1) {
+                S = sm.s0[par];
+#pragma unroll
+                for (int s = 0; s < G::HS; ++s) {
+                    int row, col;
+                    if (halo_pos(threadIdx.x + s * G::NT, row, col)) S[row * G::L0W + col] = P.halo[s];
+                }
+            } else {
+                S = sm.s1[t - 2][par];
+            }
+#pragma unroll
+            for (int r = 0; r < PY; ++r)
+                S[(th.wv * PY + r + M) * W + th.lane + COFF] = qu[t - 1][r][pjb<PH>(M + 1)];
+            publish<t + 1, PH>(sm, th, qu, P, par);
+        }
     }
 
-    __device__ static __forceinline__ void load(const SweepArgs &a, Pre &P, int i, int x0, int xend,
-                                                const int32_t (&yz)[PY], const bool (&din)[PY],
-                                                const int32_t (&hg)[G::HS])
+    // Position (row, col) in the level-0 LDS plane of halo slot h; false if unused.
+    __device__ static __forceinline__ bool halo_pos(int h, int &row, int &col)
     {
-        const bool hin = (unsigned)i < (unsigned)a.nx;
-        const float *hp = a.u0 + (int64_t)(hin ? i : 0) * a.sxy;
+        if (h < 2 * M * G::L0W) {
+            const int band = h / G::L0W;
+            col = h - band * G::L0W;
+            row = band < M ? band : band + G::RY;
+        } else {
+            const int h2 = h - 2 * M * G::L0W;
+            row = M + h2 / (2 * M);
+            const int cj = h2 % (2 * M);
+            col = cj < M ? cj : cj + G::RZ;
+        }
+        return h < G::NHALO;
+    }
+
+    // Planes level t must produce: [x0 - (T - t) M, xend + (T - t) M) within the grid.
+    __device__ static __forceinline__ bool needed(const SweepArgs &a, const Thread &th, int t, int c)
+    {
+        return (unsigned)c < (unsigned)a.nx && c >= th.x0 - (T - t) * M &&
+               c < th.xend + (T - t) * M;
+    }
+
+    // Issue the loads of iteration i: head plane i of u^n; level-0 halo ring and
+    // u^{n-1} at plane i - M; q at every level's plane i - t M.
+    __device__ static __forceinline__ void load(const SweepArgs &a, const Thread &th, Pre &P, int i)
+    {
+        const auto rh = plane_rsrc(a.u0, i, a.sxy, (unsigned)i < (unsigned)a.nx);
 #pragma unroll
-        for (int r = 0; r < PY; ++r) P.head[r] = (hin && din[r]) ? hp[yz[r]] : 0.0f;
+        for (int r = 0; r < PY; ++r) P.head[r] = bload(rh, th.bo[r]);
         const int c1 = i - M;
-        const bool l1 = needed(a, 1, c1, x0, xend);
-        const bool cin = (unsigned)c1 < (unsigned)a.nx;
-        const float *cp = a.u0 + (int64_t)(cin ? c1 : 0) * a.sxy;
+        const bool l1 = needed(a, th, 1, c1);
+        const auto rc = plane_rsrc(a.u0, c1, a.sxy, l1);
 #pragma unroll
-        for (int s = 0; s < G::HS; ++s) P.halo[s] = (l1 && hg[s] >= 0) ? cp[hg[s]] : 0.0f;
-        const float *mp = a.um + (int64_t)(cin ? c1 : 0) * a.sxy;
+        for (int s = 0; s < G::HS; ++s) P.halo[s] = bload(rc, th.hb[s]);
+        const auto rm = plane_rsrc(a.um, c1, a.sxy, l1);
 #pragma unroll
-        for (int r = 0; r < PY; ++r) P.up1[r] = (l1 && din[r]) ? mp[yz[r]] : 0.0f;
+        for (int r = 0; r < PY; ++r) P.up1[r] = bload(rm, th.bo[r]);
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int ct = i - t * M;
-            const bool lt = needed(a, t, ct, x0, xend);
-            const float *qp = a.q + (int64_t)(lt ? ct : 0) * a.sxy;
+            const auto rq = plane_rsrc(a.q, ct, a.sxy, needed(a, th, t, ct));
 #pragma unroll
-            for (int r = 0; r < PY; ++r) P.q[t - 1][r] = (lt && din[r]) ? qp[yz[r]] : 0.0f;
+            for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload(rq, th.bo[r]);
         }
     }
 
     // Process level t (1..T) at plane c = i - t*M, then recurse to level t+1.
-    template <int t, class QU, class ACC>
-    __device__ static __forceinline__ void level(const SweepArgs &a, Smem &sm, QU &qu, ACC &acc,
-                                                 float (&val)[PY], const Pre &P,
-                                                 int i, int par, int x0, int xend, int64_t N,
-                                                 int lane, int wv, const int32_t (&yz)[PY],
-                                                 const bool (&din)[PY], const float (&pyz)[PY],
-                                                 const bool (&core)[PY])
+    template <int t, int PH, class QU, class ACC>
+    __device__ static __forceinline__ void level(const SweepArgs &a, Smem &sm, const Thread &th,
+                                                 QU &qu, ACC &acc, float (&val)[PY], const Pre &P,
+                                                 int i, int par, int64_t N)
     {
-        constexpr int Q = G::Q;
         const int c = i - t * M;
-        // shift level t's queue and push the newest plane (c + M)
+        const int lane = th.lane, wv = th.wv;
+        // push the newest plane (c + M) into level t's queue
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
+            if constexpr (ROT) {
+                qu[t - 1][r][PH] = val[r];  // the slot of the oldest entry
+            } else {
 #pragma unroll
-            for (int j = 0; j + 1 < Q; ++j) qu[t - 1][r][j] = qu[t - 1][r][j + 1];
-            qu[t - 1][r][Q - 1] = val[r];
+                for (int j = 0; j + 1 < Q; ++j) qu[t - 1][r][j] = qu[t - 1][r][j + 1];
+                qu[t - 1][r][Q - 1] = val[r];
+            }
         }
-        // publish the centre plane c of u^{t-1} for y/z neighbours
-        float *S;
+        // level t's y/z plane (published before this iteration's barrier)
         constexpr int W = (t == 1) ? G::L0W : G::RZ;
         constexpr int OFF = M;          // row offset (and, for t == 1, column offset)
         constexpr int COFF = (t == 1) ? M : 0;
-        if constexpr (t == 1) {
-            S = sm.s0[par];
-#pragma unroll
-            for (int s = 0; s < G::HS; ++s)
-                if (threadIdx.x + s * G::NT < G::NHALO) {
-                    // slot positions are recomputed from the slot index (cheap, no registers)
-                    const int h = threadIdx.x + s * G::NT;
-                    int row, col;
-                    if (h < 2 * M * G::L0W) {
-                        const int band = h / G::L0W;
-                        col = h - band * G::L0W;
-                        row = band < M ? band : band + G::RY;
-                    } else {
-                        const int h2 = h - 2 * M * G::L0W;
-                        row = M + h2 / (2 * M);
-                        const int cj = h2 % (2 * M);
-                        col = cj < M ? cj : cj + G::RZ;
-                    }
-                    S[row * G::L0W + col] = P.halo[s];
-                }
-        } else {
-            S = sm.s1[t - 2][par];
-        }
-#pragma unroll
-        for (int r = 0; r < PY; ++r) S[(wv * PY + r + OFF) * W + lane + COFF] = qu[t - 1][r][M];
-        __syncthreads();
+        const float *S;
+        if constexpr (t == 1) S = sm.s0[par];
+        else S = sm.s1[t - 2][par];
 
         // level t's region: owned region shrunk by M (t - 1)
         constexpr int lo = M * (t - 1);
         const bool xin = (unsigned)c < (unsigned)a.nx;
         const bool zreg = lane >= lo && lane < G::RZ - lo;
         float out[PY];
-        if (needed(a, t, c, x0, xend)) {
-            const float pxv = a.px[c];
+        if (needed(a, th, t, c)) {
+            const int tj = c - th.cbase;  // index into the per-plane tables
+            const float pxv = sm.px[tj];
             // y neighbours: rows above / below the thread's PY rows come from LDS
             float colv[PY + 2 * M];
 #pragma unroll
@@ -268,64 +367,70 @@ struct StreamKernel {
                 colv[M + PY + j] = S[(wv * PY + PY + j + OFF) * W + lane + COFF];
             }
 #pragma unroll
-            for (int r = 0; r < PY; ++r) colv[M + r] = qu[t - 1][r][M];
+            for (int r = 0; r < PY; ++r) colv[M + r] = qu[t - 1][r][pj<PH>(M)];
 #pragma unroll
             for (int r = 0; r < PY; ++r) {
+                // computed for every owned point (all operands are finite: loads
+                // outside the grid read as 0); points outside the grid or the
+                // level's region are then set to 0
                 const int rr = wv * PY + r;
-                const bool active = din[r] && zreg && rr >= lo && rr < G::RY - lo;
-                float o = 0.0f;
-                if (active) {
-                    const float uc = qu[t - 1][r][M];
-                    const float *row = S + (rr + OFF) * W + lane + COFF;
-                    float lap = 0.0f;
+                const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
+                const float uc = qu[t - 1][r][pj<PH>(M)];
+                const float *row = S + (rr + OFF) * W + lane + COFF;
+                float lap = 0.0f;
 #pragma unroll
-                    for (int k = 1; k <= M; ++k) {
-                        const float xs = qu[t - 1][r][M - k] + qu[t - 1][r][M + k];
-                        const float ys = colv[M + r - k] + colv[M + r + k];
-                        const float zs = row[-k] + row[k];
+                for (int k = 1; k <= M; ++k) {
+                    const float xs = qu[t - 1][r][pj<PH>(M - k)] + qu[t - 1][r][pj<PH>(M + k)];
+                    const float ys = colv[M + r - k] + colv[M + r + k];
+                    const float zs = row[-k] + row[k];
+                    if constexpr (ISO) {
+                        lap = fmaf(a.w.wx[k - 1], fmaf(a.w.cc, uc, (xs + ys) + zs), lap);
+                    } else {
                         lap = fmaf(a.w.wx[k - 1], fmaf(-2.0f, uc, xs), lap);
                         lap = fmaf(a.w.wy[k - 1], fmaf(-2.0f, uc, ys), lap);
                         lap = fmaf(a.w.wz[k - 1], fmaf(-2.0f, uc, zs), lap);
                     }
-                    const float qv = P.q[t - 1][r];
-                    float up;
-                    if constexpr (t == 1) up = P.up1[r];
-                    else up = qu[t - 2][r][0];
-                    const float eta = qv * (pxv + pyz[r]);
-                    const float num = fmaf(qv, lap, fmaf(eta - 1.0f, up, 2.0f * uc));
-                    o = num;
-                    if (eta != 0.0f) o = num / (1.0f + eta);
                 }
-                out[r] = o;
+                const float qv = P.q[t - 1][r];
+                float up;
+                if constexpr (t == 1) up = P.up1[r];
+                else up = qu[t - 2][r][pj<PH>(0)];
+                const float eta = qv * (pxv + th.pyz[r]);
+                const float num = fmaf(qv, lap, fmaf(eta - 1.0f, up, 2.0f * uc));
+                float o = num;
+                if (eta != 0.0f) o = num / (1.0f + eta);
+                out[r] = active ? o : 0.0f;
             }
             const int step = a.step0 + t - 1;
-            if (a.inj.cnt > 0) {
-                const int jb = a.inj.xptr[c], je = a.inj.xptr[c + 1];
+            {
+                const int jb = __builtin_amdgcn_readfirstlane(sm.ixp[tj]);
+                const int je = __builtin_amdgcn_readfirstlane(sm.ixp[tj + 1]);
                 if (jb < je) {
                     const float *arow = a.amp + (a.abase + (int64_t)a.adir * step) * a.inj.stride;
                     for (int j = jb; j < je; ++j) {
-                        const int32_t p = a.inj.yz[j];
+                        const uint32_t p = (uint32_t)a.inj.yz[j] * 4u;
                         const float sc = a.inj.scale[j];
                         const float w = arow[a.inj.id[j]];
 #pragma unroll
                         for (int r = 0; r < PY; ++r) {
                             const int rr = wv * PY + r;
-                            const bool active = din[r] && zreg && rr >= lo && rr < G::RY - lo;
-                            if (active && yz[r] == p) out[r] = fmaf(sc, w, out[r]);
+                            const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
+                            if (active && th.bo[r] == p) out[r] = fmaf(sc, w, out[r]);
                         }
                     }
                 }
             }
-            const bool own = c >= x0 && c < xend;
-            if (own && a.rec.cnt > 0) {
-                const int jb = a.rec.xptr[c], je = a.rec.xptr[c + 1];
+            const bool own = c >= th.x0 && c < th.xend;
+            if (own) {
+                const int jb = __builtin_amdgcn_readfirstlane(sm.rxp[tj]);
+                const int je = __builtin_amdgcn_readfirstlane(sm.rxp[tj + 1]);
                 if (jb < je) {
                     float *orow = a.rec_out + (a.rbase + (int64_t)a.rdir * step) * a.rec.stride;
                     for (int j = jb; j < je; ++j) {
-                        const int32_t p = a.rec.yz[j];
+                        const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
 #pragma unroll
                         for (int r = 0; r < PY; ++r)
-                            if (core[r] && yz[r] == p) orow[a.rec.id[j]] = out[r] * a.rscale;
+                            if (th.core[r] && th.bo[r] == p) orow[a.rec.id[j]] = out[r] * a.rscale;
                     }
                 }
             }
@@ -335,11 +440,11 @@ struct StreamKernel {
                                 (int64_t)c * a.sxy;
 #pragma unroll
                     for (int r = 0; r < PY; ++r) {
-                        if (core[r]) {
+                        if (th.core[r]) {
                             float um;
                             if constexpr (t == 1) um = P.up1[r];
-                            else um = qu[t - 2][r][0];
-                            dp[yz[r]] = fmaf(-2.0f, qu[t - 1][r][M], out[r]) + um;
+                            else um = qu[t - 2][r][pj<PH>(0)];
+                            *at(dp, th.bo[r]) = fmaf(-2.0f, qu[t - 1][r][pj<PH>(M)], out[r]) + um;
                         }
                     }
                 }
@@ -352,12 +457,13 @@ struct StreamKernel {
                     constexpr int J = (T - t) * M;
 #pragma unroll
                     for (int r = 0; r < PY; ++r) {
-                        if (core[r]) {
+                        if (th.core[r]) {
+                            const uint32_t e = th.bo[r] >> 2;
                             double base;
-                            if constexpr (t == 1) base = gp[yz[r]];
+                            if constexpr (t == 1) base = gp[e];
                             else base = acc[r][J];
-                            const double nv = fma((double)out[r], (double)dp[yz[r]], base);
-                            if constexpr (t == T) gp[yz[r]] = nv;
+                            const double nv = fma((double)out[r], (double)ld(dp, th.bo[r]), base);
+                            if constexpr (t == T) gp[e] = nv;
                             else acc[r][J] = nv;
                         }
                     }
@@ -370,30 +476,30 @@ struct StreamKernel {
 
         if constexpr (t == T) {
             // the pass's outputs at plane c: u^{n+T} and (T >= 2) u^{n+T-1}
-            if (xin && c >= x0 && c < xend) {
+            if (xin && c >= th.x0 && c < th.xend) {
                 float *o1 = a.o1 + (int64_t)c * a.sxy;
 #pragma unroll
                 for (int r = 0; r < PY; ++r)
-                    if (core[r]) o1[yz[r]] = out[r];
+                    if (th.core[r]) *at(o1, th.bo[r]) = out[r];
                 if constexpr (T >= 2) {
                     float *o2 = a.o2 + (int64_t)c * a.sxy;
 #pragma unroll
                     for (int r = 0; r < PY; ++r)
-                        if (core[r]) o2[yz[r]] = qu[T - 1][r][M];
+                        if (th.core[r]) *at(o2, th.bo[r]) = qu[T - 1][r][pj<PH>(M)];
                 }
             }
         } else {
 #pragma unroll
             for (int r = 0; r < PY; ++r) val[r] = out[r];
-            level<t + 1>(a, sm, qu, acc, val, P, i, par, x0, xend, N, lane, wv, yz, din, pyz, core);
+            level<t + 1, PH>(a, sm, th, qu, acc, val, P, i, par, N);
         }
     }
 };
 
-template <int M, int T, int PY, int NW, int MODE>
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
 __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 {
-    using K = StreamKernel<M, T, PY, NW, MODE>;
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
     __shared__ typename K::Smem sm;
     K::run(a, sm);
 }

@@ -7,8 +7,9 @@ namespace fdw {
 template <int M, int T, int PY, int NW, int MODE>
 static void launch_one(const SweepArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE>), dim3(a.ntz * a.nty * a.ntx), dim3(64 * NW), 0,
-                       s, a);
+    const dim3 grid(a.ntz * a.nty * a.ntx), block(64 * NW);
+    if (a.w.iso) hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, false>), grid, block, 0, s, a);
 }
 
 #define FDW_LAUNCH_CASE(M_, T_, PY_, NW_, MODE_)                                          \
