@@ -142,3 +142,60 @@ def autotune(shape, h, so, dt, device="cuda", sponge=0, vref=1500.0, nt=8, varia
 
 def last_config():
     return L.fd_last_config()
+
+
+def _shot_struct(sh, op, keep):
+    """Fill an fd_shot from a dict (v, h, so, nt, dt, src_idx, src_amp, rec_idx, [d_obs], options)."""
+    v = _dev_f32(sh["v"], "v")
+    nd = v.dim()
+    s = L.fd_shot()
+    s.grid = L.make_grid(tuple(v.shape), sh["h"], sh["so"], sh.get("sponge", 0), sh.get("vref", 1500.0))
+    s.time = L.make_time(sh["nt"], sh["dt"])
+    s.v = L._ptr(v)
+    src = L.Points(sh["src_idx"], _dev_f32(sh["src_amp"], "src_amp"), nd)
+    d_obs = sh.get("d_obs")
+    rec = L.Points(sh["rec_idx"], None if d_obs is None else _dev_f32(d_obs, "d_obs"), nd)
+    s.src = src.s
+    s.rec = rec.s
+    out = {}
+    if op == L.FD_OP_FORWARD:
+        out["rec"] = torch.zeros((int(sh["nt"]), rec.n), dtype=torch.float32, device=v.device)
+        s.rec_out = L._ptr(out["rec"]) if rec.n else None
+    else:
+        out["grad_v"] = torch.zeros(tuple(v.shape), dtype=torch.float32, device=v.device)
+        s.grad_v = L._ptr(out["grad_v"])
+    s.opts = _opts(**sh.get("options", {}))
+    keep += [v, src, rec, out]
+    return s, out
+
+
+def forward_batch(shots, graph=True):
+    """Forward sweeps of many shots (uneven grids / orders); returns a list of trace tensors."""
+    keep, outs = [], []
+    arr = (L.fd_shot * len(shots))()
+    for i, sh in enumerate(shots):
+        arr[i], o = _shot_struct(sh, L.FD_OP_FORWARD, keep)
+        outs.append(o)
+    nbytes = L.fd_batch_workspace_size(len(shots), arr, L.FD_OP_FORWARD)
+    dev = shots[0]["v"].device
+    ws = _workspace(nbytes, dev)
+    rc = L.fd_forward_batch(len(shots), arr, L._ptr(ws), ws.numel(), L.FD_BATCH_GRAPH if graph else 0,
+                            L._stream(dev))
+    L._check(rc, "fd_forward_batch")
+    return [o["rec"] for o in outs]
+
+
+def gradient_batch(shots, graph=True):
+    """Least-squares gradients of many shots; returns (misfits, list of grad_v tensors)."""
+    keep, outs = [], []
+    arr = (L.fd_shot * len(shots))()
+    for i, sh in enumerate(shots):
+        arr[i], o = _shot_struct(sh, L.FD_OP_GRADIENT, keep)
+        outs.append(o)
+    nbytes = L.fd_batch_workspace_size(len(shots), arr, L.FD_OP_GRADIENT)
+    dev = shots[0]["v"].device
+    ws = _workspace(nbytes, dev)
+    rc = L.fd_gradient_batch(len(shots), arr, L._ptr(ws), ws.numel(), L.FD_BATCH_GRAPH if graph else 0,
+                             L._stream(dev))
+    L._check(rc, "fd_gradient_batch")
+    return [float(arr[i].misfit) for i in range(len(shots))], [o["grad_v"] for o in outs]

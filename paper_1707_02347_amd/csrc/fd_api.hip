@@ -8,10 +8,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fdwave.h"
@@ -49,6 +51,63 @@ bool launch_stream(const KernelKey &k, const SweepArgs &a, hipStream_t s)
     case 8: return launch_stream_m8(k, a, s);
     default: return false;
     }
+}
+
+bool launch_group_m1(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m2(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m3(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m4(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m5(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m6(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m7(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+bool launch_group_m8(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
+int occupancy_m1(const KernelKey &, bool);
+int occupancy_m2(const KernelKey &, bool);
+int occupancy_m3(const KernelKey &, bool);
+int occupancy_m4(const KernelKey &, bool);
+int occupancy_m5(const KernelKey &, bool);
+int occupancy_m6(const KernelKey &, bool);
+int occupancy_m7(const KernelKey &, bool);
+int occupancy_m8(const KernelKey &, bool);
+
+bool launch_stream_grouped(const KernelKey &k, bool iso, const GroupEntry *list, int nlist,
+                           int total, int grid, hipStream_t s)
+{
+    switch (k.M) {
+    case 1: return launch_group_m1(k, iso, list, nlist, total, grid, s);
+    case 2: return launch_group_m2(k, iso, list, nlist, total, grid, s);
+    case 3: return launch_group_m3(k, iso, list, nlist, total, grid, s);
+    case 4: return launch_group_m4(k, iso, list, nlist, total, grid, s);
+    case 5: return launch_group_m5(k, iso, list, nlist, total, grid, s);
+    case 6: return launch_group_m6(k, iso, list, nlist, total, grid, s);
+    case 7: return launch_group_m7(k, iso, list, nlist, total, grid, s);
+    case 8: return launch_group_m8(k, iso, list, nlist, total, grid, s);
+    default: return false;
+    }
+}
+
+int stream_occupancy(const KernelKey &k, bool iso)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(k.M, k.T, k.PY, k.NW, k.mode, iso ? 1 : 0);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    switch (k.M) {
+    case 1: n = occupancy_m1(k, iso); break;
+    case 2: n = occupancy_m2(k, iso); break;
+    case 3: n = occupancy_m3(k, iso); break;
+    case 4: n = occupancy_m4(k, iso); break;
+    case 5: n = occupancy_m5(k, iso); break;
+    case 6: n = occupancy_m6(k, iso); break;
+    case 7: n = occupancy_m7(k, iso); break;
+    case 8: n = occupancy_m8(k, iso); break;
+    default: break;
+    }
+    cache[key] = n;
+    return n;
 }
 
 bool stream_has(const KernelKey &k)
@@ -513,12 +572,59 @@ PointTable as_table(const TableBufs &b, int stride, int cnt, bool with_scale)
     return t;
 }
 
+// ------------------------------------------------------------------ execution
+// Device work of a sweep is issued through an Exec: immediately on its stream,
+// or recorded as a list of ops (kernel passes kept as (key, arguments) so that
+// a batch can merge the passes of many shots into grouped launches).
+struct Op {
+    bool is_pass = false;
+    KernelKey key{};
+    SweepArgs a{};
+    std::function<hipError_t(hipStream_t)> call;
+};
+
+struct Exec {
+    hipStream_t s = nullptr;
+    std::vector<Op> *rec = nullptr;
+    void pass(const KernelKey &k, const SweepArgs &a)
+    {
+        if (!stream_has(k)) throw Status{FD_EUNSUPPORTED};
+        if (rec) {
+            Op o;
+            o.is_pass = true;
+            o.key = k;
+            o.a = a;
+            rec->push_back(std::move(o));
+            return;
+        }
+        launch_stream(k, a, s);
+        FDW_HIP(hipGetLastError());
+    }
+    template <class F>
+    void call(F f)
+    {
+        if (rec) {
+            Op o;
+            o.call = f;
+            rec->push_back(std::move(o));
+            return;
+        }
+        FDW_HIP(f(s));
+    }
+};
+
+hipError_t copy_async(float *dst, const float *src, int64_t n, hipStream_t s)
+{
+    return hipMemcpyAsync(dst, src, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+}
+
 // ------------------------------------------------------------------ per-call context
 struct Ctx {
     Dims d;
     int64_t nt;
     double dt;
     hipStream_t s;
+    Exec ex;
     Plan plan;
     Layout L;
     SweepArgs base;   // common launch arguments
@@ -653,12 +759,16 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             a.um = st.prev;
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
             a.o1 = out;
-            FDW_HIP(launch_naive_step(d.M, a, c.s));
-            FDW_HIP(launch_inject(a, out, a.step0, c.s));
-            FDW_HIP(launch_record(a, out, a.step0, c.s));
-            if (so.mode == kSaveD2)
-                FDW_HIP(launch_save_d2(a, out, st.cur, st.prev, a.d2 + a.dslot0 * d.N, c.s));
-            if (so.mode == kImaging) FDW_HIP(launch_imaging(a, out, a.d2 + a.dslot0 * d.N, a.g, c.s));
+            const int M = d.M, mode = so.mode;
+            float *cur = st.cur, *prev = st.prev, *d2 = a.d2 + a.dslot0 * d.N;
+            c.ex.call([a, M, out, cur, prev, d2, mode](hipStream_t s) {
+                hipError_t e = launch_naive_step(M, a, s);
+                if (e == hipSuccess) e = launch_inject(a, out, a.step0, s);
+                if (e == hipSuccess) e = launch_record(a, out, a.step0, s);
+                if (e == hipSuccess && mode == kSaveD2) e = launch_save_d2(a, out, cur, prev, d2, s);
+                if (e == hipSuccess && mode == kImaging) e = launch_imaging(a, out, d2, a.g, s);
+                return e;
+            });
             swap_in(st, out, st.cur);
             s += 1;
             continue;
@@ -686,8 +796,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.ntz = (d.nz + tz - 1) / tz;
         a.nty = (d.ny + ty - 1) / ty;
         a.ntx = (d.nx + a.lx - 1) / a.lx;
-        if (!launch_stream(k, a, c.s)) throw Status{FD_EUNSUPPORTED};
-        FDW_HIP(hipGetLastError());
+        c.ex.pass(k, a);
         if (Tk == 1) swap_in(st, o1, st.cur);
         else swap_in(st, o1, o2);
         s += Tk;
@@ -760,6 +869,81 @@ int ws_check(void *ws, size_t ws_bytes, size_t need)
 
 }  // namespace
 
+// fd_forward in two phases: setup (eager) and issue (through c.ex).
+struct FwdJob {
+    Ctx c;
+    float *u_state = nullptr;
+    int nr = 0;
+    uint32_t flags = 0;
+};
+
+int fwd_setup(FwdJob &j, const fd_grid *grid, const fd_time *time, const float *v,
+              const fd_points *src, const fd_points *rec, float *rec_out, float *u_state,
+              void *workspace, size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    Ctx &c = j.c;
+    int rc = validate_common(grid, time, v, c.d);
+    if (rc) return rc;
+    if ((rc = check_points(c.d, src, true, time->nt))) return rc;
+    if ((rc = check_points(c.d, rec, false, time->nt))) return rc;
+    j.nr = rec ? rec->n : 0;
+    if (j.nr > 0 && time->nt > 0 && !rec_out) return FD_EINVAL;
+    c.nt = time->nt;
+    c.dt = time->dt;
+    c.s = (hipStream_t)stream;
+    c.ex.s = c.s;
+    if ((rc = make_plan(c.d, opts, c.plan))) return rc;
+    const int ns = src ? src->n : 0;
+    c.L = layout(nullptr, c.d, c.nt, ns, j.nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+    if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
+    c.L = layout(workspace, c.d, c.nt, ns, j.nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+    j.flags = opts ? opts->flags : 0u;
+    if ((rc = prepare(c, grid, v, src, 1.0f, rec, j.flags))) return rc;
+    c.base.amp = src ? src->amp : nullptr;
+    c.base.rec_out = rec_out;
+    j.u_state = u_state;
+    return FD_OK;
+}
+
+void fwd_issue(FwdJob &j)
+{
+    Ctx &c = j.c;
+    const int64_t N = c.d.N;
+    float *A, *B;
+    if (j.u_state) {
+        A = j.u_state;
+        B = j.u_state + N;
+    } else {
+        A = c.L.fields[2];
+        B = c.L.fields[3];
+        c.ex.call([A, B, N](hipStream_t s) {
+            hipError_t e = launch_zero(A, N * 4, s);
+            return e == hipSuccess ? launch_zero(B, N * 4, s) : e;
+        });
+    }
+    State st;
+    st.cur = A;
+    st.prev = B;
+    st.spare[0] = c.L.fields[0];
+    st.spare[1] = c.L.fields[1];
+    st.spare[2] = nullptr;
+    st.nspare = 2;
+    advance(c, st, 0, c.nt, StepOpts{});
+    if (j.u_state) {
+        const State fin = st;
+        float *tmp = (c.L.fields[0] == st.cur || c.L.fields[0] == st.prev) ? c.L.fields[1]
+                                                                            : c.L.fields[0];
+        c.ex.call([fin, A, B, tmp, N](hipStream_t s) {
+            try {
+                place_state(fin, A, B, tmp, N, s);
+            } catch (const HipFail &f) {
+                return f.e;
+            }
+            return hipSuccess;
+        });
+    }
+}
+
 }  // namespace fdw
 
 using namespace fdw;
@@ -809,47 +993,13 @@ int fd_forward(const fd_grid *grid, const fd_time *time, const float *v, const f
                size_t ws_bytes, const fd_options *opts, void *stream)
 {
     return guarded([&]() -> int {
-        Ctx c;
-        int rc = validate_common(grid, time, v, c.d);
+        FwdJob j;
+        int rc = fwd_setup(j, grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts,
+                           stream);
         if (rc) return rc;
-        if ((rc = check_points(c.d, src, true, time->nt))) return rc;
-        if ((rc = check_points(c.d, rec, false, time->nt))) return rc;
-        const int nr = rec ? rec->n : 0;
-        if (nr > 0 && time->nt > 0 && !rec_out) return FD_EINVAL;
-        c.nt = time->nt;
-        c.dt = time->dt;
-        c.s = (hipStream_t)stream;
-        if ((rc = make_plan(c.d, opts, c.plan))) return rc;
-        const int ns = src ? src->n : 0;
-        c.L = layout(nullptr, c.d, c.nt, ns, nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
-        if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
-        c.L = layout(workspace, c.d, c.nt, ns, nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
-        const uint32_t flags = opts ? opts->flags : 0u;
-        if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
-        c.base.amp = src ? src->amp : nullptr;
-        c.base.rec_out = rec_out;
-        State st;
-        float *A, *B;
-        if (u_state) {
-            A = u_state;
-            B = u_state + c.d.N;
-        } else {
-            A = c.L.fields[2];
-            B = c.L.fields[3];
-            FDW_HIP(launch_zero(A, c.d.N * 4, c.s));
-            FDW_HIP(launch_zero(B, c.d.N * 4, c.s));
-        }
-        st.cur = A;
-        st.prev = B;
-        st.spare[0] = c.L.fields[0];
-        st.spare[1] = c.L.fields[1];
-        st.spare[2] = nullptr;
-        st.nspare = 2;
-        advance(c, st, 0, c.nt, StepOpts{});
-        if (u_state) place_state(st, A, B, c.L.fields[0] == st.cur || c.L.fields[0] == st.prev
-                                               ? c.L.fields[1] : c.L.fields[0], c.d.N, c.s);
-        record_last(c.plan);
-        if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, c.nt * nr, c.s);
+        fwd_issue(j);
+        record_last(j.c.plan);
+        if (j.flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, j.c.nt * j.nr, j.c.s);
         return FD_OK;
     });
 }
@@ -869,6 +1019,7 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
         c.nt = time->nt;
         c.dt = time->dt;
         c.s = (hipStream_t)stream;
+        c.ex.s = c.s;
         if ((rc = make_plan(c.d, opts, c.plan))) return rc;
         c.L = layout(nullptr, c.d, c.nt, nr, ns, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
         if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
@@ -910,92 +1061,131 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
 namespace fdw {
 namespace {
 
-// Shared body of fd_gradient / fd_vjp.  y == nullptr: residual d - d_obs
-// (d_obs = rec->amp) and misfit; otherwise y is the trace cotangent.
-int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
-                  const fd_points *rec, const float *y, float *grad_v, double *misfit,
-                  float *residual, void *workspace, size_t ws_bytes, const fd_options *opts,
-                  void *stream, int op)
-{
+// fd_gradient / fd_vjp in three phases: setup (validation, tables, stability
+// check: eager, may synchronise), issue (all device work of the checkpointed
+// adjoint-state gradient, through c.ex: executed or recorded) and misfit (reads
+// the residual partial sums back).
+struct GradJob {
     Ctx c;
+    const float *v = nullptr;
+    const float *y = nullptr;      // trace cotangent (vjp) or nullptr (least squares)
+    const float *dobs = nullptr;   // observed data (least squares)
+    float *grad_v = nullptr;
+    float *residual = nullptr;     // caller's residual buffer or nullptr
+    int K = 50, ns = 0, nr = 0;
+};
+
+int grad_setup(GradJob &j, const fd_grid *grid, const fd_time *time, const float *v,
+               const fd_points *src, const fd_points *rec, const float *y, float *grad_v,
+               float *residual, void *workspace, size_t ws_bytes, const fd_options *opts,
+               void *stream, int op)
+{
+    Ctx &c = j.c;
     int rc = validate_common(grid, time, v, c.d);
     if (rc) return rc;
     if ((rc = check_points(c.d, src, true, time->nt))) return rc;
     if ((rc = check_points(c.d, rec, true, time->nt))) return rc;
     if (!grad_v) return FD_EINVAL;
-    const int ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+    j.ns = src ? src->n : 0;
+    j.nr = rec ? rec->n : 0;
     c.nt = time->nt;
     c.dt = time->dt;
     c.s = (hipStream_t)stream;
+    c.ex.s = c.s;
     if ((rc = make_plan(c.d, opts, c.plan))) return rc;
-    const int K = ckpt_interval(opts);
-    if (K < 1) return FD_EINVAL;
-    c.L = layout(nullptr, c.d, c.nt, ns, nr, op, fields_needed(op), K);
+    j.K = ckpt_interval(opts);
+    if (j.K < 1) return FD_EINVAL;
+    c.L = layout(nullptr, c.d, c.nt, j.ns, j.nr, op, fields_needed(op), j.K);
     if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
-    c.L = layout(workspace, c.d, c.nt, ns, nr, op, fields_needed(op), K);
+    c.L = layout(workspace, c.d, c.nt, j.ns, j.nr, op, fields_needed(op), j.K);
     const uint32_t flags = opts ? opts->flags : 0u;
-    const int64_t N = c.d.N;
-
-    // ---- forward sweep with checkpoints (sources inject, receivers record)
     if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
+    // adjoint injection scale at the receivers: 1 / (2m + dt damp) = q / (2 dt^2 (1 + eta))
+    const float alpha = (float)(1.0 / (2.0 * c.dt * c.dt));
+    FDW_HIP(launch_scales(c.base, as_table(c.L.rec, j.nr, c.base.rec.cnt, true), c.L.rec.scale, alpha,
+                          c.s));
     c.base.amp = src ? src->amp : nullptr;
+    j.v = v;
+    j.y = y;
+    j.dobs = rec ? rec->amp : nullptr;
+    j.grad_v = grad_v;
+    j.residual = residual;
+    return FD_OK;
+}
+
+void grad_issue(GradJob &j)
+{
+    Ctx &c = j.c;
+    const int64_t N = c.d.N;
+    const int K = j.K, ns = j.ns, nr = j.nr;
+    // ---- forward sweep with checkpoints (sources inject, receivers record)
     c.base.rec_out = c.L.traces;
     float *F[5] = {c.L.fields[0], c.L.fields[1], c.L.fields[2], c.L.fields[3], c.L.fields[4]};
     State st{F[0], F[1], {F[2], F[3], F[4]}, 3};
-    FDW_HIP(launch_zero(st.cur, N * 4, c.s));
-    FDW_HIP(launch_zero(st.prev, N * 4, c.s));
-    for (int j = 0; j < c.L.nck; ++j) {
-        const int64_t k0 = (int64_t)j * K, k1 = std::min<int64_t>(k0 + K, c.nt);
-        float *ck = c.L.ckpt + (size_t)j * 2 * N;
-        FDW_HIP(hipMemcpyAsync(ck, st.cur, N * 4, hipMemcpyDeviceToDevice, c.s));
-        FDW_HIP(hipMemcpyAsync(ck + N, st.prev, N * 4, hipMemcpyDeviceToDevice, c.s));
+    {
+        float *a0 = st.cur, *a1 = st.prev;
+        c.ex.call([a0, a1, N](hipStream_t s) {
+            hipError_t e = launch_zero(a0, N * 4, s);
+            return e == hipSuccess ? launch_zero(a1, N * 4, s) : e;
+        });
+    }
+    for (int jck = 0; jck < c.L.nck; ++jck) {
+        const int64_t k0 = (int64_t)jck * K, k1 = std::min<int64_t>(k0 + K, c.nt);
+        float *ck = c.L.ckpt + (size_t)jck * 2 * N;
+        float *cur = st.cur, *prev = st.prev;
+        c.ex.call([ck, cur, prev, N](hipStream_t s) {
+            hipError_t e = copy_async(ck, cur, N, s);
+            return e == hipSuccess ? copy_async(ck + N, prev, N, s) : e;
+        });
         advance(c, st, k0, k1 - k0, StepOpts{});
     }
-    // ---- residual / cotangent
-    const float *adj_src = y;
-    if (!y) {
-        const int nb = kStatBlocks;
-        float *res = residual ? residual : c.L.resid;
-        FDW_HIP(launch_residual(c.L.traces, rec ? rec->amp : nullptr, res, c.nt * nr, c.L.rpart, nb,
-                                c.s));
+    // ---- residual (least squares) or the given cotangent
+    const float *adj_src = j.y;
+    if (!j.y) {
+        float *res = j.residual ? j.residual : c.L.resid;
+        const float *d = c.L.traces, *dobs = j.dobs;
+        double *part = c.L.rpart;
+        const int64_t n = c.nt * nr;
+        c.ex.call([d, dobs, res, n, part](hipStream_t s) {
+            return launch_residual(d, dobs, res, n, part, kStatBlocks, s);
+        });
         adj_src = res;
-        if (misfit) {
-            std::vector<double> part(nb);
-            FDW_HIP(hipMemcpyAsync(part.data(), c.L.rpart, nb * 8, hipMemcpyDeviceToHost, c.s));
-            FDW_HIP(hipStreamSynchronize(c.s));
-            double J = 0.0;
-            for (double p : part) J += p;
-            *misfit = J;
-        }
     }
     // ---- adjoint sweep with segment recomputation and imaging
     SweepArgs fwd = c.base;
     fwd.rec = as_table(c.L.rec, nr, 0, false);  // no recording during recomputation
     SweepArgs adj = c.base;
+    adj.inj = as_table(c.L.rec, nr, c.base.rec.cnt, true);
+    adj.rec = as_table(c.L.src, ns, 0, false);
+    adj.amp = adj_src;
+    adj.abase = c.nt - 1;
+    adj.adir = -1;
+    adj.rec_out = nullptr;
     {
-        // adjoint: receivers inject the residual with scale 1 / (2m + dt damp)
-        // (computed into the receiver table's scale slots); nothing is recorded
-        const float alpha = (float)(1.0 / (2.0 * c.dt * c.dt));
-        FDW_HIP(launch_scales(c.base, as_table(c.L.rec, nr, c.base.rec.cnt, true), c.L.rec.scale,
-                              alpha, c.s));
-        adj.inj = as_table(c.L.rec, nr, c.base.rec.cnt, true);
-        adj.rec = as_table(c.L.src, ns, 0, false);
-        adj.amp = adj_src;
-        adj.abase = c.nt - 1;
-        adj.adir = -1;
-        adj.rec_out = nullptr;
+        double *g = c.L.g;
+        c.ex.call([g, N](hipStream_t s) { return launch_zero(g, N * 8, s); });
     }
-    FDW_HIP(launch_zero(c.L.g, N * 8, c.s));
     float *Aa[4] = {c.L.fields[5], c.L.fields[6], c.L.fields[7], c.L.fields[8]};
     State sa{Aa[0], Aa[1], {Aa[2], Aa[3], nullptr}, 2};
-    FDW_HIP(launch_zero(sa.cur, N * 4, c.s));
-    FDW_HIP(launch_zero(sa.prev, N * 4, c.s));
-    for (int j = c.L.nck - 1; j >= 0; --j) {
-        const int64_t k0 = (int64_t)j * K, k1 = std::min<int64_t>(k0 + K, c.nt);
-        const float *ck = c.L.ckpt + (size_t)j * 2 * N;
+    {
+        float *a0 = sa.cur, *a1 = sa.prev;
+        c.ex.call([a0, a1, N](hipStream_t s) {
+            hipError_t e = launch_zero(a0, N * 4, s);
+            return e == hipSuccess ? launch_zero(a1, N * 4, s) : e;
+        });
+    }
+    const SweepArgs saved = c.base;
+    for (int jck = c.L.nck - 1; jck >= 0; --jck) {
+        const int64_t k0 = (int64_t)jck * K, k1 = std::min<int64_t>(k0 + K, c.nt);
+        const float *ck = c.L.ckpt + (size_t)jck * 2 * N;
         State sf{F[0], F[1], {F[2], F[3], F[4]}, 3};
-        FDW_HIP(hipMemcpyAsync(sf.cur, ck, N * 4, hipMemcpyDeviceToDevice, c.s));
-        FDW_HIP(hipMemcpyAsync(sf.prev, ck + N, N * 4, hipMemcpyDeviceToDevice, c.s));
+        {
+            float *cur = sf.cur, *prev = sf.prev;
+            c.ex.call([ck, cur, prev, N](hipStream_t s) {
+                hipError_t e = copy_async(cur, ck, N, s);
+                return e == hipSuccess ? copy_async(prev, ck + N, N, s) : e;
+            });
+        }
         c.base = fwd;
         StepOpts fo;
         fo.mode = kSaveD2;
@@ -1010,8 +1200,37 @@ int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, cons
         ao.ddir = -1;
         advance(c, sa, c.nt - k1, k1 - k0, ao);
     }
-    FDW_HIP(launch_grad_v(c.L.g, v, grad_v, N, c.s));
-    record_last(c.plan);
+    c.base = saved;
+    {
+        const double *g = c.L.g;
+        const float *v = j.v;
+        float *gv = j.grad_v;
+        c.ex.call([g, v, gv, N](hipStream_t s) { return launch_grad_v(g, v, gv, N, s); });
+    }
+}
+
+double grad_misfit(GradJob &j)
+{
+    std::vector<double> part(kStatBlocks);
+    FDW_HIP(hipMemcpyAsync(part.data(), j.c.L.rpart, kStatBlocks * 8, hipMemcpyDeviceToHost, j.c.s));
+    FDW_HIP(hipStreamSynchronize(j.c.s));
+    double J = 0.0;
+    for (double p : part) J += p;
+    return J;
+}
+
+int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+                  const fd_points *rec, const float *y, float *grad_v, double *misfit,
+                  float *residual, void *workspace, size_t ws_bytes, const fd_options *opts,
+                  void *stream, int op)
+{
+    GradJob j;
+    int rc = grad_setup(j, grid, time, v, src, rec, y, grad_v, residual, workspace, ws_bytes, opts,
+                        stream, op);
+    if (rc) return rc;
+    grad_issue(j);
+    if (!y && misfit) *misfit = grad_misfit(j);
+    record_last(j.c.plan);
     return FD_OK;
 }
 
@@ -1124,6 +1343,7 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         c.nt = tt.nt;
         c.dt = tt.dt;
         c.s = s;
+        c.ex.s = s;
         c.L = layout(workspace, d, tt.nt, 0, 0, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
         // a constant medium at 60 % of the stability limit: kernel time does not
         // depend on the values, only on the sponge branch, which is kept
@@ -1206,56 +1426,214 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
 }
 
 // ====================================================================== batches
+namespace fdw {
+namespace {
+
+int device_cus()
+{
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
+// Upper bound of grouped-pass entries a shot contributes (one per step per sweep).
+size_t entry_bound(const fd_shot &sh, int op)
+{
+    const int64_t nt = std::max<int64_t>(sh.time.nt, 0);
+    return (size_t)((op == FD_OP_GRADIENT ? 3 : 1) * nt + 8);
+}
+
+// Merge the recorded op lists of many shots and run them on one stream: ops
+// are taken round by round (op r of every shot), passes of one round with the
+// same kernel configuration and Laplacian form become one grouped persistent
+// launch over all their tiles, other ops run as recorded.  Shots are
+// independent, so any interleaving that keeps each shot's order is valid.
+int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_t max_entries,
+               bool graph, hipStream_t s)
+{
+    struct Launch {
+        bool grouped;
+        KernelKey key;
+        bool iso;
+        size_t off;
+        int n, total;
+        int shot, idx;
+        int grid;
+    };
+    const int cus = device_cus();
+    std::vector<GroupEntry> host;
+    std::vector<Launch> plan;
+    size_t rounds = 0;
+    for (auto &o : ops) rounds = std::max(rounds, o.size());
+    for (size_t r = 0; r < rounds; ++r) {
+        std::vector<std::pair<size_t, size_t>> passes;  // (shot, op) of this round
+        for (size_t sh = 0; sh < ops.size(); ++sh) {
+            if (r >= ops[sh].size()) continue;
+            if (ops[sh][r].is_pass) passes.push_back({sh, r});
+            else plan.push_back(Launch{false, {}, false, 0, 0, 0, (int)sh, (int)r, 0});
+        }
+        std::vector<bool> done(passes.size(), false);
+        for (size_t p = 0; p < passes.size(); ++p) {
+            if (done[p]) continue;
+            const Op &lead = ops[passes[p].first][passes[p].second];
+            Launch L{true, lead.key, lead.a.w.iso != 0, host.size(), 0, 0, -1, -1, 0};
+            for (size_t q = p; q < passes.size(); ++q) {
+                const Op &o = ops[passes[q].first][passes[q].second];
+                const KernelKey &k = o.key;
+                if (done[q] || k.M != lead.key.M || k.T != lead.key.T || k.PY != lead.key.PY ||
+                    k.NW != lead.key.NW || k.mode != lead.key.mode || (o.a.w.iso != 0) != L.iso)
+                    continue;
+                done[q] = true;
+                GroupEntry e{};
+                e.a = o.a;
+                e.a.remap = 0;
+                e.tile0 = L.total;
+                L.total += o.a.ntz * o.a.nty * o.a.ntx;
+                host.push_back(e);
+                ++L.n;
+            }
+            // persistent grid: every resident workgroup slot of the device, at most one per tile
+            L.grid = std::min(L.total, std::max(1, stream_occupancy(L.key, L.iso)) * cus);
+            plan.push_back(L);
+        }
+    }
+    if (host.size() > max_entries) return FD_EWORKSPACE;
+    if (!host.empty())
+        FDW_HIP(hipMemcpyAsync(dev_entries, host.data(), host.size() * sizeof(GroupEntry),
+                               hipMemcpyHostToDevice, s));
+    FDW_HIP(hipStreamSynchronize(s));
+    auto issue = [&](hipStream_t st) {
+        for (const Launch &L : plan) {
+            if (L.grouped) {
+                if (!launch_stream_grouped(L.key, L.iso, dev_entries + L.off, L.n, L.total, L.grid, st))
+                    throw Status{FD_EUNSUPPORTED};
+                FDW_HIP(hipGetLastError());
+            } else {
+                FDW_HIP(ops[L.shot][L.idx].call(st));
+            }
+        }
+    };
+    if (!graph) {
+        issue(s);
+        return FD_OK;
+    }
+    // capture on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured), replay on the caller's stream
+    hipStream_t cs = nullptr;
+    FDW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        throw HipFail{e};
+    }
+    int status = FD_OK;
+    try {
+        issue(cs);
+    } catch (const HipFail &f) {
+        e = f.e;
+    } catch (const Status &st) {
+        status = st.code;
+    }
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess && status == FD_OK) e = ec;
+    if (e == hipSuccess && status == FD_OK) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess && status == FD_OK) e = hipGraphLaunch(ge, s);
+    if (e == hipSuccess && status == FD_OK) e = hipStreamSynchronize(s);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (status != FD_OK) return status;
+    if (e != hipSuccess) throw HipFail{e};
+    return FD_OK;
+}
+
+size_t shot_ws(const fd_shot &sh, int op)
+{
+    return (fd_workspace_size(&sh.grid, &sh.time, &sh.src, &sh.rec, &sh.opts, op) + 255) &
+           ~(size_t)255;
+}
+
+}  // namespace
+}  // namespace fdw
+
 extern "C" size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int op)
 {
     if (nshots < 0 || (nshots > 0 && !shots)) return 0;
     if (op != FD_OP_FORWARD && op != FD_OP_GRADIENT) return 0;
-    size_t total = 0;
+    size_t total = 0, entries = 0;
     for (int i = 0; i < nshots; ++i) {
         const size_t b = fd_workspace_size(&shots[i].grid, &shots[i].time, &shots[i].src,
                                            &shots[i].rec, &shots[i].opts, op);
         if (!b) return 0;
         total += (b + 255) & ~(size_t)255;
+        entries += entry_bound(shots[i], op);
     }
-    return total;
+    return total + ((entries * sizeof(GroupEntry) + 255) & ~(size_t)255) + 256;
 }
 
 extern "C" int fd_forward_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
                                 uint32_t batch_flags, void *stream)
 {
-    if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
-    const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_FORWARD);
-    if (nshots > 0 && (!workspace || ws_bytes < need)) return FD_EWORKSPACE;
-    (void)batch_flags;
-    size_t off = 0;
-    for (int i = 0; i < nshots; ++i) {
-        fd_shot &sh = shots[i];
-        const size_t b = fd_workspace_size(&sh.grid, &sh.time, &sh.src, &sh.rec, &sh.opts,
-                                           FD_OP_FORWARD);
-        const int rc = fd_forward(&sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, sh.rec_out, nullptr,
-                                  (char *)workspace + off, b, &sh.opts, stream);
-        if (rc) return rc;
-        off += (b + 255) & ~(size_t)255;
-    }
-    return FD_OK;
+    return guarded([&]() -> int {
+        if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
+        if (nshots == 0) return FD_OK;
+        const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_FORWARD);
+        if (!need) return FD_EINVAL;
+        if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) return FD_EWORKSPACE;
+        std::vector<FwdJob> jobs(nshots);
+        std::vector<std::vector<Op>> ops(nshots);
+        size_t off = 0, entries = 0;
+        for (int i = 0; i < nshots; ++i) {
+            fd_shot &sh = shots[i];
+            const size_t b = shot_ws(sh, FD_OP_FORWARD);
+            const int rc = fwd_setup(jobs[i], &sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, sh.rec_out,
+                                     nullptr, (char *)workspace + off, b, &sh.opts, stream);
+            if (rc) return rc;
+            jobs[i].c.ex.rec = &ops[i];
+            fwd_issue(jobs[i]);
+            off += b;
+            entries += entry_bound(sh, FD_OP_FORWARD);
+        }
+        return run_merged(ops, (GroupEntry *)((char *)workspace + off), entries,
+                          (batch_flags & FD_BATCH_GRAPH) != 0, (hipStream_t)stream);
+    });
 }
 
 extern "C" int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
                                  uint32_t batch_flags, void *stream)
 {
-    if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
-    const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_GRADIENT);
-    if (nshots > 0 && (!workspace || ws_bytes < need)) return FD_EWORKSPACE;
-    (void)batch_flags;
-    size_t off = 0;
-    for (int i = 0; i < nshots; ++i) {
-        fd_shot &sh = shots[i];
-        const size_t b = fd_workspace_size(&sh.grid, &sh.time, &sh.src, &sh.rec, &sh.opts,
-                                           FD_OP_GRADIENT);
-        const int rc = fd_gradient(&sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, sh.grad_v, &sh.misfit,
-                                   nullptr, (char *)workspace + off, b, &sh.opts, stream);
+    return guarded([&]() -> int {
+        if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
+        if (nshots == 0) return FD_OK;
+        const size_t need = fd_batch_workspace_size(nshots, shots, FD_OP_GRADIENT);
+        if (!need) return FD_EINVAL;
+        if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) return FD_EWORKSPACE;
+        std::vector<GradJob> jobs(nshots);
+        std::vector<std::vector<Op>> ops(nshots);
+        size_t off = 0, entries = 0;
+        for (int i = 0; i < nshots; ++i) {
+            fd_shot &sh = shots[i];
+            const size_t b = shot_ws(sh, FD_OP_GRADIENT);
+            const int rc = grad_setup(jobs[i], &sh.grid, &sh.time, sh.v, &sh.src, &sh.rec, nullptr,
+                                      sh.grad_v, nullptr, (char *)workspace + off, b, &sh.opts,
+                                      stream, FD_OP_GRADIENT);
+            if (rc) return rc;
+            jobs[i].c.ex.rec = &ops[i];
+            grad_issue(jobs[i]);
+            off += b;
+            entries += entry_bound(sh, FD_OP_GRADIENT);
+        }
+        const int rc = run_merged(ops, (GroupEntry *)((char *)workspace + off), entries,
+                                  (batch_flags & FD_BATCH_GRAPH) != 0, (hipStream_t)stream);
         if (rc) return rc;
-        off += (b + 255) & ~(size_t)255;
-    }
-    return FD_OK;
+        for (int i = 0; i < nshots; ++i) shots[i].misfit = grad_misfit(jobs[i]);
+        return FD_OK;
+    });
 }

@@ -77,14 +77,28 @@ struct SweepArgs {
 
 enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
 
+// One shot's pass in a grouped launch: its arguments and the index of its
+// first tile in the launch's flat tile range (entries sorted by tile0).
+struct GroupEntry {
+    SweepArgs a;
+    int32_t tile0;
+    int32_t pad[3];
+};
+
 // Stream/time-block kernel configuration (compile-time template parameters).
 struct KernelKey {
     int M, T, PY, NW, mode;
 };
 
 // Launcher for the templated streaming kernel; returns false when no
-// instantiation matches the key.
+// instantiation matches the key.  With list == nullptr the kernel runs the
+// tiles of `a`; otherwise it walks the `total` tiles of the nlist entries
+// persistently with `grid` workgroups (iso selects the Laplacian form).
 bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
+bool launch_stream_grouped(const KernelKey &key, bool iso, const GroupEntry *list, int nlist,
+                           int total, int grid, hipStream_t s);
+// Resident workgroups per CU of a configuration (0 if not compiled).
+int stream_occupancy(const KernelKey &key, bool iso);
 // Tile sizes (core rows / columns) for a key.
 int stream_core_rows(const KernelKey &key);
 int stream_core_cols(const KernelKey &key);

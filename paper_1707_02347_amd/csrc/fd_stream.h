@@ -134,11 +134,10 @@ struct StreamKernel {
         bool hv[G::HS];     // halo slot inside the grid
     };
 
-    __device__ static void run(const SweepArgs &a, Smem &sm)
+    // Run tile `bid` of the ntiles tiles of one shot's pass.
+    __device__ static void run(const SweepArgs &a, Smem &sm, int bid, int ntiles)
     {
         // -------- tile decode (optionally XCD-aware: consecutive tiles on one XCD)
-        int bid = blockIdx.x;
-        const int ntiles = gridDim.x;
         if (a.remap && (ntiles & 7) == 0) {
             const int per = ntiles >> 3;
             bid = (bid & 7) * per + (bid >> 3);
@@ -496,12 +495,25 @@ struct StreamKernel {
     }
 };
 
+// Single pass (list == nullptr: workgroup b runs tile b of a0) or grouped
+// persistent pass (workgroups walk the flat tile range of all list entries).
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
-__global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
+__global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a0, const GroupEntry *list, int nlist,
+                                                    int total)
 {
     using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
     __shared__ typename K::Smem sm;
-    K::run(a, sm);
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        if (list == nullptr) {
+            K::run(a0, sm, item, total);
+        } else {
+            int e = 0;
+            while (e + 1 < nlist && list[e + 1].tile0 <= item) ++e;
+            const SweepArgs &a = list[e].a;
+            K::run(a, sm, item - list[e].tile0, a.ntz * a.nty * a.ntx);
+        }
+        __syncthreads();  // the next tile rewrites the LDS tables and planes
+    }
 }
 
 }  // namespace fdw
