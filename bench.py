@@ -80,12 +80,16 @@ def workload(name, device="cuda"):
                 amp=torch.from_numpy(amp).to(device), rec=rec, sponge=L, vref=4500.0)
 
 
-# Launch configuration of each workload's time-tiled sweep (chosen by the
-# library's autotuner on MI355X).
+# Launch configurations (tile = (planes per workgroup along x, tile rows,
+# rows per thread)), chosen from MI355X sweeps of the library's autotuner search
+# space: for these workloads the space-tiled kernel (T = 1) is the fastest;
+# the time-blocked T = 2 kernel is reported beside it.
 TUNED = {
-    "cfg2": dict(variant=3, tile=(0, 32, 8), tblock=2),
-    "cfg3": dict(variant=3, tile=(0, 32, 4), tblock=2),
-    "cfg4": dict(variant=3, tile=(0, 32, 8), tblock=2),
+    "cfg2": dict(variant=2, tile=(16, 32, 4)),
+    "cfg2_t2": dict(variant=3, tblock=2, tile=(64, 32, 2)),
+    "cfg3": dict(variant=2, tile=(64, 32, 8)),
+    "cfg3_t2": dict(variant=3, tblock=2, tile=(64, 32, 4)),
+    "cfg4": dict(variant=2, tile=(16, 32, 8)),
 }
 
 
@@ -93,27 +97,55 @@ def launch_options(name):
     return dict(TUNED.get(name, dict(variant=2)))
 
 
+def kernel_source_hash():
+    """Hash of the sweep kernel sources (counter data is only valid for these)."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in ("fd_stream.h", "fd_stream_configs.h", "fd_stream_m4.hip"):
+        h.update(open(os.path.join(HERE, "paper_1707_02347_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    counter summary, if it was taken with the current kernel source."""
+    path = os.path.join(HERE, "profiles", "k_stream_cfg2_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _sweep(cs, opts, nt=None):
     from paper_1707_02347_amd import api
 
-    return api.forward(cs["v"], cs["h"], cs["so"], cs["nt"] if nt is None else nt, cs["dt"], cs["src"],
-                       cs["amp"] if nt is None else cs["amp"][: max(nt, 0)].contiguous(), cs["rec"],
-                       sponge=cs["sponge"], vref=cs["vref"], **opts)
+    n = cs["nt"] if nt is None else nt
+    return api.forward(cs["v"], cs["h"], cs["so"], n, cs["dt"], cs["src"], cs["amp"][: max(n, 0)].contiguous(),
+                       cs["rec"], sponge=cs["sponge"], vref=cs["vref"], **opts)
 
 
-def time_sweeps(cs, opts, steps, warmup):
-    """Median/mean/std ms of whole sweeps, bracketed by synchronisations, HIP events."""
+def _timed(fn, reps, warmup):
     import torch
 
     for _ in range(warmup):
-        _sweep(cs, opts)
+        fn()
     torch.cuda.synchronize()
     times = []
-    for _ in range(steps):
+    for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        _sweep(cs, opts)
+        fn()
         e1.record()
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
@@ -122,21 +154,14 @@ def time_sweeps(cs, opts, steps, warmup):
     return float(np.median(t)), float(t.mean()), float(t.std())
 
 
+def time_sweeps(cs, opts, steps, warmup):
+    """Median / mean / std ms of whole sweeps (HIP events on the launch stream)."""
+    return _timed(lambda: _sweep(cs, opts), steps, warmup)
+
+
 def setup_ms(cs, opts, reps=3):
     """Time of a zero-step call (validation, q, tables): subtracted to get kernel time."""
-    import torch
-
-    best = 1e30
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        _sweep(cs, opts, nt=0)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1))
-    return best
+    return _timed(lambda: _sweep(cs, opts, nt=0), reps, 1)[0]
 
 
 def oracle_baseline(cs, budget_s=15.0):
@@ -157,9 +182,90 @@ def oracle_baseline(cs, budget_s=15.0):
     steps = int(max(2, min(200, budget_s / max(t1, 1e-3))))
     t = run(steps)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": npts * steps / t / 1e9, "unit": "GPts/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} of {cs['nt']} steps of {cs['name']} at full size ({npts} points), FP64",
+    return {"value": round(npts * steps / t / 1e9, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} of the {cs['nt']} steps of {cs['name']} at full size ({npts} points), FP64",
             "seconds": round(t, 3)}
+
+
+def gradient_rate(reps=2, warmup=1):
+    """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
+    import torch
+
+    import synth
+    from paper_1707_02347_amd import api
+
+    cs = workload("cfg4")
+    vtrue = synth.blob_velocity(cs["v"], amp=0.05, width_frac=1.0 / 16.0)
+    d_obs = api.forward(vtrue, cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
+                        sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg4"))["rec"]
+    out = {}
+
+    def run():
+        out["J"], out["g"], _ = api.gradient(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"],
+                                             cs["rec"], d_obs, sponge=cs["sponge"], vref=cs["vref"], ckpt_every=50,
+                                             **launch_options("cfg4"))
+
+    med, mean, std = _timed(run, reps, warmup)
+    del d_obs
+    torch.cuda.empty_cache()
+    return {"gradients_per_s": round(1000.0 / med, 3), "ms": round(med, 1), "misfit": out["J"],
+            "config": "cfg4: 256^3 so8, 1000 steps, 256 receivers, d_obs from a +5% Gaussian blob, checkpoint 50"}
+
+
+def batch_shots(device="cuda"):
+    """cfg5: 32 seeded shots, cubic N in [128, 320], space orders {4, 8, 16}, nt in [500, 1000]."""
+    import torch
+
+    import synth
+
+    shots = []
+    for sh in synth.shot_batch(32, seed=2347):
+        n, so, nt = sh["n"], sh["so"], sh["nt"]
+        shape = (n, n, n)
+        v = synth.smooth_velocity(shape, seed=sh["vseed"], sigma=8.0, device=device)
+        dt = 0.8 * courant_max(so, 3) * 10.0 / 4500.0
+        amp = torch.from_numpy(synth.ricker(nt, dt, 15.0)[:, None].copy()).to(device)
+        shots.append(dict(v=v, h=[10.0] * 3, so=so, nt=nt, dt=dt, src_idx=synth.centre_source(shape, depth=20),
+                          src_amp=amp, rec_idx=synth.receiver_line(shape, 128, depth=20), sponge=20, vref=4500.0,
+                          options=dict(variant=2, ckpt_every=50)))
+    return shots
+
+
+def batch_rates():
+    """Batched forward and gradients of cfg5 vs the same shots one by one with the untiled kernel."""
+    import torch
+
+    import synth
+    from paper_1707_02347_amd import api
+
+    shots = batch_shots()
+    pts = sum(float(np.prod(s["v"].shape)) * s["nt"] for s in shots)
+    res = {}
+    med, _, _ = _timed(lambda: api.forward_batch(shots, graph=True), 1, 1)
+    res["forward_batched_gpts"] = round(pts / (med * 1e-3) / 1e9, 2)
+
+    def sequential_untiled():
+        for s in shots:
+            api.forward(s["v"], s["h"], s["so"], s["nt"], s["dt"], s["src_idx"], s["src_amp"], s["rec_idx"],
+                        sponge=s["sponge"], vref=s["vref"], variant=1)
+
+    med_u, _, _ = _timed(sequential_untiled, 1, 0)
+    res["forward_sequential_untiled_gpts"] = round(pts / (med_u * 1e-3) / 1e9, 2)
+    # observed data from a perturbed model, then all 32 gradients in one batch
+    traces = api.forward_batch([dict(s, v=synth.blob_velocity(s["v"], 0.05, 1.0 / 16.0)) for s in shots])
+    for s, d in zip(shots, traces):
+        s["d_obs"] = d
+    t0 = time.perf_counter()
+    misfits, grads = api.gradient_batch(shots, graph=True)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    res["gradients_batched_per_s"] = round(len(shots) / tg, 3)
+    res["gradient_batch_s"] = round(tg, 2)
+    res["shots"] = len(shots)
+    res["point_steps"] = pts
+    del grads, traces
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -169,6 +275,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--headline-only-kernel", action="store_true",
+                    help="only the headline tiled sweep (for profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -179,55 +289,92 @@ def main():
 
     from paper_1707_02347_amd import api
 
-    dev = "cuda"
-    cs = workload("cfg2", dev)
+    if args.copy_probe:
+        n = 256 * 1024 * 1024
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        ms = _timed(lambda: y.copy_(x), 5, 2)[0]
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return 0
+    cs = workload("cfg2")
     npts = int(np.prod(cs["v"].shape))
     tiled = launch_options("cfg2")
-    variants = {"untiled": dict(variant=1), "space_tiled": dict(variant=2), "time_tiled": tiled}
+    if args.headline_only_kernel:
+        for _ in range(args.warmup + args.steps):
+            _sweep(cs, tiled)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "cfg2 tiled", "sweeps": args.warmup + args.steps}), flush=True)
+        return 0
+    print(f"# cfg2 {cs['v'].shape} so{cs['so']} nt{cs['nt']}", file=sys.stderr, flush=True)
+    variants = {"untiled": dict(variant=1), "tiled": tiled, "time_tiled_T2": launch_options("cfg2_t2")}
     res = {}
     for k, o in variants.items():
-        med, mean, std = time_sweeps(cs, o, args.steps if k == "time_tiled" else max(2, args.steps // 2),
-                                     args.warmup)
+        med, mean, std = time_sweeps(cs, o, args.steps, args.warmup)
         res[k] = dict(ms=med, mean_ms=mean, std_ms=std, gpts=npts * cs["nt"] / (med * 1e-3) / 1e9)
-    cfg_used = api.last_config()
-    api.forward(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], None,
-                sponge=cs["sponge"], vref=cs["vref"], **tiled)
+    _sweep(cs, tiled)
     cfg_used = api.last_config()
 
-    # roofline of the dominant kernel (the time-blocked sweep kernel)
-    T = cfg_used["tblock"]
+    # roofline of the dominant kernel: the tiled sweep kernel of the headline
+    T = int(cfg_used["tblock"])
     setup = setup_ms(cs, tiled)
-    launches = cs["nt"] // T + (cs["nt"] % T)
-    kern_ms = max(res["time_tiled"]["ms"] - setup, 1e-6) / launches
+    launches = cs["nt"] // T + cs["nt"] % T
+    kern_ms = max(res["tiled"]["ms"] - setup, 1e-6) / launches
     bytes_per_launch = (20 if T >= 2 else 16) * npts
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    traffic = profiled_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_stream M=4 T={T}", "avg_launch_us": round(kern_ms * 1e3, 2),
-            "bytes_per_launch": bytes_per_launch}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_stream<M=4,T={T},PY={cfg_used['tile'][2]},NW={cfg_used['tile'][1] // cfg_used['tile'][2]}>",
+            "avg_launch_us": round(kern_ms * 1e3, 2), "launches": launches, "bytes_per_launch": bytes_per_launch,
+            "bytes_per_point": 20 if T >= 2 else 16}
     line = {
         "metric": METRIC,
-        "value": round(res["time_tiled"]["gpts"], 2),
+        "value": round(res["tiled"]["gpts"], 2),
         "unit": "GPts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(res["time_tiled"]["ms"], 3),
+        "ms_per_step": round(res["tiled"]["ms"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "cfg2: 3-D 256^3, space order 8, 500 steps, smoothed random v "
-                               "(seed 1707, sigma 8, 1.5-4.5 km/s), 15 Hz Ricker at depth 20, 20-cell "
-                               "sponge, time-tiled", "launch": cfg_used, "parallelism": "single GPU"},
+        "config": {"workload": "cfg2: 3-D 256^3, space order 8, 500 steps, smoothed random v (seed 1707, "
+                               "sigma 8 cells, 1.5-4.5 km/s), 15 Hz Ricker at depth 20, 20-cell sponge; one "
+                               "step = one whole 500-step sweep; tiled kernel from the autotuner's search "
+                               "space (time-block depth 1 wins on MI355X, T = 2 reported beside)",
+                   "launch": cfg_used, "parallelism": "single GPU"},
         "roofline": roof,
-        "bw_equiv_frac_16B": round(res["time_tiled"]["gpts"] * 16 / HBM_PEAK_GBS, 4),
+        "bw_equiv_frac_16B": round(res["tiled"]["gpts"] * 16 / HBM_PEAK_GBS, 4),
         "variants_gpts": {k: round(v["gpts"], 2) for k, v in res.items()},
-        "variants_ms": {k: [round(v["ms"], 3), round(v["mean_ms"], 3), round(v["std_ms"], 3)]
-                        for k, v in res.items()},
+        "variants_ms_median_mean_std": {k: [round(v["ms"], 3), round(v["mean_ms"], 3), round(v["std_ms"], 3)]
+                                        for k, v in res.items()},
     }
+    if not args.quick:
+        print("# cfg3", file=sys.stderr, flush=True)
+        c3 = workload("cfg3")
+        n3 = int(np.prod(c3["v"].shape))
+        r3 = {}
+        for k, o in {"tiled": launch_options("cfg3"), "time_tiled_T2": launch_options("cfg3_t2"),
+                     "untiled": dict(variant=1)}.items():
+            med, _, _ = time_sweeps(c3, o, 1, 1)
+            r3[k] = round(n3 * c3["nt"] / (med * 1e-3) / 1e9, 2)
+        line["cfg3_512cube_so16_gpts"] = r3
+        line["cfg3_bw_equiv_frac_16B"] = round(r3["tiled"] * 16 / HBM_PEAK_GBS, 4)
+        del c3
+        torch.cuda.empty_cache()
+        print("# cfg4", file=sys.stderr, flush=True)
+        line["cfg4_fwi_gradient"] = gradient_rate()
+        print("# cfg5", file=sys.stderr, flush=True)
+        try:
+            line["cfg5_batched"] = batch_rates()
+        except Exception as e:  # report, do not lose the line
+            line["cfg5_batched"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     if not args.no_oracle:
+        print("# oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = oracle_baseline(cs)
     print(json.dumps(line), flush=True)
     return 0

@@ -1,7 +1,9 @@
 """Build libfdwave.so for gfx950 in-tree with hipcc.
 
-Every .hip source in this directory is compiled to an object in parallel,
-then linked into ``paper_1707_02347_amd/libfdwave.so``.  Flags:
+Every .hip source in this directory, plus one generated source per kernel
+configuration listed in fd_stream_configs.h (and the generated registry of
+those configurations), is compiled to an object in parallel, then linked into
+``paper_1707_02347_amd/libfdwave.so``.  Flags:
 
 * ``--offload-arch=gfx950``: MI355X only.
 * ``-ffp-contract=off``: no implicit FMA contraction; the kernels write every
@@ -13,6 +15,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -29,12 +32,65 @@ FLAGS = [
 ]
 
 
+GEN = os.path.join(BUILD, "gen")
+
+
+def configs():
+    """(M, T, PY, NW, MODE, F) tuples of every X(...) entry in fd_stream_configs.h."""
+    text = open(os.path.join(HERE, "fd_stream_configs.h")).read()
+    text = text.replace("FDW_AG", "3").replace("FDW_A", "1").replace("FDW_G", "2")
+    out = []
+    for m in re.finditer(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", text):
+        out.append(tuple(int(g) for g in m.groups()))
+    if len(set(out)) != len(out):
+        raise RuntimeError("duplicate kernel configuration in fd_stream_configs.h")
+    return out
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path) and open(path).read() == text:
+        return
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def generate():
+    """One source per configuration and the registry; returns their paths."""
+    os.makedirs(GEN, exist_ok=True)
+    paths, names = [], []
+    for cfg in configs():
+        name = "kEntry_%d_%d_%d_%d_%d" % cfg[:5]
+        names.append(name)
+        args = "%d, %d, %d, %d, %d, %d" % cfg
+        text = ('// generated from fd_stream_configs.h\n#include "%s/fd_stream.h"\n#include "%s/fd_stream_entry.h"\n'
+                "namespace fdw {\nextern StreamEntry %s;\nStreamEntry %s = {%s, &entry_launch<%s>,\n"
+                "    &entry_launch_group<%s>, &entry_occupancy<%s>};\n}  // namespace fdw\n"
+                % (HERE, HERE, name, name, args, args, args, args))
+        path = os.path.join(GEN, name + ".hip")
+        _write_if_changed(path, text)
+        paths.append(path)
+    reg = ['// generated from fd_stream_configs.h', '#include "%s/fd_stream_entry.h"' % HERE, "namespace fdw {"]
+    reg += ["extern StreamEntry %s;" % n for n in names]
+    reg += ["static const StreamEntry *const kRegistry[] = {"] + ["    &%s," % n for n in names] + ["};"]
+    reg += ["const StreamEntry *const *stream_registry(int *count)", "{",
+            "    *count = (int)(sizeof(kRegistry) / sizeof(kRegistry[0]));", "    return kRegistry;", "}",
+            "}  // namespace fdw", ""]
+    path = os.path.join(GEN, "fd_registry.hip")
+    _write_if_changed(path, "\n".join(reg))
+    paths.append(path)
+    return paths
+
+
 def sources():
-    return sorted(os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".hip"))
+    own = sorted(os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".hip"))
+    return own + generate()
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+    deps = [src] + [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".h")]
+    if os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps):
+        return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -42,10 +98,18 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, clean: bool = False) -> str:
+    """Compile and link; objects newer than their sources and headers are reused
+    unless clean=True."""
     os.makedirs(BUILD, exist_ok=True)
+    if clean:
+        for f in os.listdir(BUILD):
+            if f.endswith(".o"):
+                os.remove(os.path.join(BUILD, f))
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    # longest compiles first: generated kernel files
+    srcs.sort(key=lambda p: (0 if os.path.basename(p).startswith("kEntry") else 1, p))
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

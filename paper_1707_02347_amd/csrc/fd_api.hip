@@ -18,72 +18,33 @@
 
 #include "../../include/fdwave.h"
 #include "fd_internal.h"
+#include "fd_stream_entry.h"
 
 namespace fdw {
 
-bool launch_stream_m1(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m2(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m3(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m4(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m5(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m6(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m7(const KernelKey &, const SweepArgs &, hipStream_t);
-bool launch_stream_m8(const KernelKey &, const SweepArgs &, hipStream_t);
-bool has_stream_m1(const KernelKey &);
-bool has_stream_m2(const KernelKey &);
-bool has_stream_m3(const KernelKey &);
-bool has_stream_m4(const KernelKey &);
-bool has_stream_m5(const KernelKey &);
-bool has_stream_m6(const KernelKey &);
-bool has_stream_m7(const KernelKey &);
-bool has_stream_m8(const KernelKey &);
+// ------------------------------------------------------------------ configuration registry
+const StreamEntry *find_entry(const KernelKey &k)
+{
+    int n = 0;
+    const StreamEntry *const *reg = stream_registry(&n);
+    for (int i = 0; i < n; ++i) {
+        const StreamEntry *e = reg[i];
+        if (e->M == k.M && e->T == k.T && e->PY == k.PY && e->NW == k.NW && e->mode == k.mode) return e;
+    }
+    return nullptr;
+}
 
 bool launch_stream(const KernelKey &k, const SweepArgs &a, hipStream_t s)
 {
-    switch (k.M) {
-    case 1: return launch_stream_m1(k, a, s);
-    case 2: return launch_stream_m2(k, a, s);
-    case 3: return launch_stream_m3(k, a, s);
-    case 4: return launch_stream_m4(k, a, s);
-    case 5: return launch_stream_m5(k, a, s);
-    case 6: return launch_stream_m6(k, a, s);
-    case 7: return launch_stream_m7(k, a, s);
-    case 8: return launch_stream_m8(k, a, s);
-    default: return false;
-    }
+    const StreamEntry *e = find_entry(k);
+    return e && e->launch(a, s);
 }
-
-bool launch_group_m1(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m2(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m3(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m4(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m5(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m6(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m7(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-bool launch_group_m8(const KernelKey &, bool, const GroupEntry *, int, int, int, hipStream_t);
-int occupancy_m1(const KernelKey &, bool);
-int occupancy_m2(const KernelKey &, bool);
-int occupancy_m3(const KernelKey &, bool);
-int occupancy_m4(const KernelKey &, bool);
-int occupancy_m5(const KernelKey &, bool);
-int occupancy_m6(const KernelKey &, bool);
-int occupancy_m7(const KernelKey &, bool);
-int occupancy_m8(const KernelKey &, bool);
 
 bool launch_stream_grouped(const KernelKey &k, bool iso, const GroupEntry *list, int nlist,
                            int total, int grid, hipStream_t s)
 {
-    switch (k.M) {
-    case 1: return launch_group_m1(k, iso, list, nlist, total, grid, s);
-    case 2: return launch_group_m2(k, iso, list, nlist, total, grid, s);
-    case 3: return launch_group_m3(k, iso, list, nlist, total, grid, s);
-    case 4: return launch_group_m4(k, iso, list, nlist, total, grid, s);
-    case 5: return launch_group_m5(k, iso, list, nlist, total, grid, s);
-    case 6: return launch_group_m6(k, iso, list, nlist, total, grid, s);
-    case 7: return launch_group_m7(k, iso, list, nlist, total, grid, s);
-    case 8: return launch_group_m8(k, iso, list, nlist, total, grid, s);
-    default: return false;
-    }
+    const StreamEntry *e = find_entry(k);
+    return e && e->launch_group(iso, list, nlist, total, grid, s);
 }
 
 int stream_occupancy(const KernelKey &k, bool iso)
@@ -94,35 +55,22 @@ int stream_occupancy(const KernelKey &k, bool iso)
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    int n = 0;
-    switch (k.M) {
-    case 1: n = occupancy_m1(k, iso); break;
-    case 2: n = occupancy_m2(k, iso); break;
-    case 3: n = occupancy_m3(k, iso); break;
-    case 4: n = occupancy_m4(k, iso); break;
-    case 5: n = occupancy_m5(k, iso); break;
-    case 6: n = occupancy_m6(k, iso); break;
-    case 7: n = occupancy_m7(k, iso); break;
-    case 8: n = occupancy_m8(k, iso); break;
-    default: break;
-    }
+    const StreamEntry *e = find_entry(k);
+    const int n = e ? e->occupancy(iso) : 0;
     cache[key] = n;
     return n;
 }
 
-bool stream_has(const KernelKey &k)
+bool stream_has(const KernelKey &k, bool iso)
 {
-    switch (k.M) {
-    case 1: return has_stream_m1(k);
-    case 2: return has_stream_m2(k);
-    case 3: return has_stream_m3(k);
-    case 4: return has_stream_m4(k);
-    case 5: return has_stream_m5(k);
-    case 6: return has_stream_m6(k);
-    case 7: return has_stream_m7(k);
-    case 8: return has_stream_m8(k);
-    default: return false;
-    }
+    const StreamEntry *e = find_entry(k);
+    return e && (iso || (e->flags & 1));
+}
+
+bool stream_has_group(const KernelKey &k, bool iso)
+{
+    const StreamEntry *e = find_entry(k);
+    return e && (e->flags & 2) && (iso || (e->flags & 1));
 }
 
 int stream_core_rows(const KernelKey &k) { return k.NW * k.PY - 2 * k.M * (k.T - 1); }
@@ -256,6 +204,8 @@ Weights make_weights(const Dims &d)
     if (iso && ref != w.wx) std::memcpy(w.wx, ref, sizeof(float) * kMaxM);
     return w;
 }
+
+bool grid_iso(const Dims &d) { return make_weights(d).iso != 0; }
 
 // Symbol of the stencil at the Nyquist wavenumber: -c0 - 2 sum_k (-1)^k c_k.
 double nyquist_symbol(int M)
@@ -436,15 +386,18 @@ int default_lx(const Dims &d, const KernelKey &k)
     return std::min(std::min(std::max(lx, 1), d.nx), kMaxLx);
 }
 
+bool grid_iso(const Dims &d);
+
 KernelKey default_key(const Dims &d, int T)
 {
+    const bool iso = grid_iso(d);
     // measured on MI355X: small-PY tiles win for T = 1, a tall (2 rows x 16
     // waves) tile for T >= 2; fall back to whatever is compiled
     static const int pref1[][2] = {{4, 4}, {4, 8}, {8, 4}};
     static const int pref2[][2] = {{2, 16}, {4, 8}, {8, 4}};
     for (auto &sh : (T == 1 ? pref1 : pref2)) {
         KernelKey k{d.M, T, sh[0], sh[1], kPlain};
-        if (stream_has(k)) return k;
+        if (stream_has(k, iso)) return k;
     }
     return KernelKey{d.M, 1, 8, 4, kPlain};
 }
@@ -485,7 +438,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         const int rows = eff.tile[1] > 0 ? eff.tile[1] : 32;
         if (rows % PY) return FD_EUNSUPPORTED;
         k = KernelKey{d.M, T, PY, rows / PY, kPlain};
-        if (!stream_has(k)) return FD_EUNSUPPORTED;
+        if (!stream_has(k, grid_iso(d))) return FD_EUNSUPPORTED;
     } else {
         k = default_key(d, T);
         if (k.T != T) {
@@ -499,16 +452,16 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
 }
 
 // Key with the same tile for another mode / depth, falling back to T = 1 (8, 4).
-KernelKey key_for(const KernelKey &base, int T, int mode)
+KernelKey key_for(const KernelKey &base, int T, int mode, bool iso)
 {
     KernelKey k = base;
     k.T = T;
     k.mode = mode;
-    if (stream_has(k)) return k;
+    if (stream_has(k, iso)) return k;
     k = KernelKey{base.M, T, 8, 4, mode};
-    if (stream_has(k)) return k;
+    if (stream_has(k, iso)) return k;
     k = KernelKey{base.M, T, 4, 8, mode};
-    if (stream_has(k)) return k;
+    if (stream_has(k, iso)) return k;
     return KernelKey{base.M, 1, 8, 4, mode};
 }
 
@@ -588,7 +541,7 @@ struct Exec {
     std::vector<Op> *rec = nullptr;
     void pass(const KernelKey &k, const SweepArgs &a)
     {
-        if (!stream_has(k)) throw Status{FD_EUNSUPPORTED};
+        if (!stream_has(k, a.w.iso != 0)) throw Status{FD_EUNSUPPORTED};
         if (rec) {
             Op o;
             o.is_pass = true;
@@ -774,9 +727,10 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             continue;
         }
         const int T = (nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+        const bool iso = c.base.w.iso != 0;
         KernelKey k = (T == c.plan.key.T && so.mode == kPlain) ? c.plan.key
-                                                                : key_for(c.plan.key, T, so.mode);
-        if (k.T != T) k = key_for(c.plan.key, 1, so.mode);
+                                                                : key_for(c.plan.key, T, so.mode, iso);
+        if (k.T != T) k = key_for(c.plan.key, 1, so.mode, iso);
         const int Tk = k.T;
         a.u0 = st.cur;
         a.um = st.prev;
@@ -1298,7 +1252,7 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
         if (fixed.tblock && fixed.tblock != T) continue;
         for (auto &sh : shapes) {
             KernelKey k{d.M, T, sh[0], sh[1], kPlain};
-            if (!stream_has(k)) continue;
+            if (!stream_has(k, grid_iso(d))) continue;
             const int lx0 = default_lx(d, k);
             for (int f : {1, 2}) {
                 const int lx = std::min(d.nx, std::max(4 * T * d.M, lx0 * f));
@@ -1412,8 +1366,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
                 found = true;
             }
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         if (!found) return FD_EUNSUPPORTED;
         *inout = best_o;
         {
@@ -1474,7 +1428,8 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
         std::vector<std::pair<size_t, size_t>> passes;  // (shot, op) of this round
         for (size_t sh = 0; sh < ops.size(); ++sh) {
             if (r >= ops[sh].size()) continue;
-            if (ops[sh][r].is_pass) passes.push_back({sh, r});
+            const Op &o = ops[sh][r];
+            if (o.is_pass && stream_has_group(o.key, o.a.w.iso != 0)) passes.push_back({sh, r});
             else plan.push_back(Launch{false, {}, false, 0, 0, 0, (int)sh, (int)r, 0});
         }
         std::vector<bool> done(passes.size(), false);
@@ -1514,7 +1469,13 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
                     throw Status{FD_EUNSUPPORTED};
                 FDW_HIP(hipGetLastError());
             } else {
-                FDW_HIP(ops[L.shot][L.idx].call(st));
+                const Op &o = ops[L.shot][L.idx];
+                if (o.is_pass) {
+                    if (!launch_stream(o.key, o.a, st)) throw Status{FD_EUNSUPPORTED};
+                    FDW_HIP(hipGetLastError());
+                } else {
+                    FDW_HIP(o.call(st));
+                }
             }
         }
     };

@@ -102,7 +102,10 @@ int stream_occupancy(const KernelKey &key, bool iso);
 // Tile sizes (core rows / columns) for a key.
 int stream_core_rows(const KernelKey &key);
 int stream_core_cols(const KernelKey &key);
-bool stream_has(const KernelKey &key);
+// Whether a configuration is compiled for the isotropic / anisotropic form, and
+// whether its grouped batch kernel is.
+bool stream_has(const KernelKey &key, bool iso);
+bool stream_has_group(const KernelKey &key, bool iso);
 
 // Naive (untiled) kernels.
 hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s);  // form from a.w.iso

@@ -32,6 +32,7 @@
 #pragma once
 
 #include "fd_internal.h"
+#include "fd_stream_entry.h"
 
 namespace fdw {
 
@@ -495,25 +496,85 @@ struct StreamKernel {
     }
 };
 
-// Single pass (list == nullptr: workgroup b runs tile b of a0) or grouped
-// persistent pass (workgroups walk the flat tile range of all list entries).
+// One pass of one shot: workgroup b runs tile b (arguments by value, so every
+// field lives in scalar registers or the kernel-argument segment).
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
-__global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a0, const GroupEntry *list, int nlist,
-                                                    int total)
+__global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
+{
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
+    __shared__ typename K::Smem sm;
+    K::run(a, sm, blockIdx.x, gridDim.x);
+}
+
+// Grouped persistent pass: the workgroups walk the flat tile range of all the
+// entries (one per shot) of a batch.
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
+__global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__restrict__ list,
+                                                            int nlist, int total)
 {
     using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
     __shared__ typename K::Smem sm;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        if (list == nullptr) {
-            K::run(a0, sm, item, total);
-        } else {
-            int e = 0;
-            while (e + 1 < nlist && list[e + 1].tile0 <= item) ++e;
-            const SweepArgs &a = list[e].a;
-            K::run(a, sm, item - list[e].tile0, a.ntz * a.nty * a.ntx);
-        }
+        int e = 0;
+        while (e + 1 < nlist && list[e + 1].tile0 <= item) ++e;
+        const SweepArgs &a = list[e].a;
+        K::run(a, sm, item - list[e].tile0, a.ntz * a.nty * a.ntx);
         __syncthreads();  // the next tile rewrites the LDS tables and planes
     }
+}
+
+// Launch helpers shared by the generated entry files.
+template <int M, int T, int PY, int NW, int MODE, int F>
+bool entry_launch(const SweepArgs &a, hipStream_t s)
+{
+    const dim3 grid(a.ntz * a.nty * a.ntx), block(64 * NW);
+    if (a.w.iso) {
+        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, true>), grid, block, 0, s, a);
+        return true;
+    }
+    if constexpr ((F & 1) != 0) {
+        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, false>), grid, block, 0, s, a);
+        return true;
+    }
+    return false;
+}
+
+template <int M, int T, int PY, int NW, int MODE, int F>
+bool entry_launch_group(bool iso, const GroupEntry *list, int nlist, int total, int grid,
+                        hipStream_t s)
+{
+    if constexpr ((F & 2) != 0) {
+        const dim3 g(grid), block(64 * NW);
+        if (iso) {
+            hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, true>), g, block, 0, s, list,
+                               nlist, total);
+            return true;
+        }
+        if constexpr ((F & 1) != 0) {
+            hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, false>), g, block, 0, s, list,
+                               nlist, total);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <int M, int T, int PY, int NW, int MODE, int F>
+int entry_occupancy(bool iso)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if constexpr ((F & 2) != 0) {
+        if (iso)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>),
+                64 * NW, 0);
+        else if constexpr ((F & 1) != 0)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>),
+                64 * NW, 0);
+    }
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace fdw
