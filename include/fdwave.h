@@ -33,8 +33,10 @@
  *   * sponge: damp(i) = sum_a d0_a (delta_a / L)^2 with delta_a the number of
  *     cells into the outer L-cell layer of axis a (0 in the interior and at the
  *     layer's inner edge) and d0_a = 1.5 ln(1000) / (vref L h_a)  [s/m^2];
- *   * stability: Courant number v_max dt / h_min must not exceed
- *     2 / sqrt(ndim * S) with S = -c_0 - 2 sum_k (-1)^k c_k.
+ *   * stability: v_max^2 dt^2 S sum_a 1/h_a^2 <= 4 with S = -c_0 - 2 sum_k (-1)^k c_k,
+ *     the largest eigenvalue of -h^2 L_h along one axis (the symbol at the Nyquist
+ *     wavenumber); for equal spacing this is the Courant bound
+ *     v_max dt / h <= 2 / sqrt(ndim S).
  *
  * Memory layout of every field: dense FP32, C order over the ndim axes, the
  * last axis contiguous (the paper's z loop is the innermost, vectorised one).
@@ -229,7 +231,9 @@ typedef struct fd_shot {
     fd_options opts;      /* per-shot options (variant/tile/tblock; 0 = auto) */
 } fd_shot;
 
-/* Workspace for a batch: the sum over shots, each rounded up to 256 bytes. */
+/* Workspace for a batch: the sum over shots of fd_workspace_size, each rounded
+ * up to 256 bytes, plus the device table of grouped-launch entries.  0 for no
+ * shots, an invalid shot or an op other than FORWARD / GRADIENT. */
 size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int op);
 
 /*

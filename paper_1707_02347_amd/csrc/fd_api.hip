@@ -1528,6 +1528,7 @@ extern "C" size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int 
 {
     if (nshots < 0 || (nshots > 0 && !shots)) return 0;
     if (op != FD_OP_FORWARD && op != FD_OP_GRADIENT) return 0;
+    if (nshots == 0) return 0;
     size_t total = 0, entries = 0;
     for (int i = 0; i < nshots; ++i) {
         const size_t b = fd_workspace_size(&shots[i].grid, &shots[i].time, &shots[i].src,
