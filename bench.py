@@ -185,7 +185,7 @@ def setup_ms(cs, opts, reps=3):
     return _timed(lambda: _sweep(cs, opts, nt=0), reps, 1)[0]
 
 
-def oracle_baseline(cs, budget_s=15.0):
+def oracle_baseline(cs, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload (a few full-size steps)."""
     import oracle
 
@@ -199,8 +199,8 @@ def oracle_baseline(cs, budget_s=15.0):
         oracle.forward(prob, amp=amp[:steps])
         return time.perf_counter() - t0
 
-    t1 = run(1)
-    steps = int(max(2, min(200, budget_s / max(t1, 1e-3))))
+    t3 = run(3) / 3.0
+    steps = int(max(2, min(500, budget_s / max(t3, 1e-3))))
     t = run(steps)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(npts * steps / t / 1e9, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
@@ -292,7 +292,7 @@ def batch_rates():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-oracle", action="store_true")
