@@ -91,6 +91,7 @@ extern "C" {
 #define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */
 #define FD_FLAG_CHECK_FINITE 2u   /* read back the traces and fail on NaN/Inf */
 #define FD_FLAG_NO_XCD_REMAP 4u   /* keep the hardware workgroup order (for A/B timing) */
+#define FD_FLAG_NO_X_ALTERNATE 8u /* stream every x-chunk upward (for A/B timing) */
 
 /* ------------------------------------------------------------------ ops for workspace sizing */
 #define FD_OP_FORWARD 0
@@ -102,7 +103,9 @@ extern "C" {
 typedef struct fd_grid {
     int32_t ndim;         /* 1, 2 or 3 */
     int32_t space_order;  /* 2, 4, 6, ..., 16 */
-    int64_t n[3];         /* points per axis (first ndim used), last axis contiguous */
+    int64_t n[3];         /* points per axis (first ndim used), last axis contiguous;
+                             1 <= n <= 2^20, and the product of the last two axes
+                             of a 3-D grid (one plane) below 2^28 */
     double h[3];          /* spacing per axis in metres, > 0 */
     int32_t sponge;       /* sponge width L in cells, 0 = none (2 L <= n[a]) */
     int32_t reserved;     /* must be 0 */

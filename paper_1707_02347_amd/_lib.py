@@ -33,6 +33,7 @@ FD_VARIANT_TBLOCK = 3
 FD_FLAG_NO_CFL_CHECK = 1
 FD_FLAG_CHECK_FINITE = 2
 FD_FLAG_NO_XCD_REMAP = 4
+FD_FLAG_NO_X_ALTERNATE = 8
 
 FD_OP_FORWARD = 0
 FD_OP_ADJOINT = 1

@@ -130,9 +130,10 @@ int make_dims(const fd_grid *g, Dims &d)
     d.ny = (int)n3[1];
     d.nz = (int)n3[2];
     d.N = n3[0] * n3[1] * n3[2];
-    // one (y, z) plane must stay below 2^29 points: kernels address a plane
-    // with 32-bit byte offsets and mark points outside the grid with offset 2^31
-    if (n3[1] * n3[2] >= ((int64_t)1 << 29)) return FD_EINVAL;
+    // one (y, z) plane must stay below 2^28 points: kernels address a plane
+    // with 32-bit byte offsets (8-byte elements for the FP64 imaging
+    // accumulator) and mark points outside the grid with offset 2^31
+    if (n3[1] * n3[2] >= ((int64_t)1 << 28)) return FD_EINVAL;
     for (int a = 0; a < 3; ++a) {
         d.h[a] = h3[a];
         d.present[a] = p3[a];
@@ -332,6 +333,7 @@ struct Plan {
     KernelKey key;    // for stream / tblock (mode set per use)
     int lx;
     bool remap;
+    bool alt;
 };
 
 std::mutex g_tune_mu;
@@ -373,13 +375,14 @@ void load_tune_file()
     std::fclose(f);
 }
 
-// Default x-chunk: enough workgroups to fill 256 CUs several times over while
-// keeping the 2 T M warm-up planes small against the chunk.
+// Default x-chunk: about 2048 waves in the launch (8 per CU of the 256; measured
+// on MI355X, more and shorter chunks re-read more warm-up planes than the extra
+// waves hide), and at least 4 T M planes so the 2 T M warm-up planes stay small.
 int default_lx(const Dims &d, const KernelKey &k)
 {
     const int ty = stream_core_rows(k), tz = stream_core_cols(k);
     const int64_t tiles = (int64_t)((d.nz + tz - 1) / tz) * ((d.ny + ty - 1) / ty);
-    const int64_t target = 2048;
+    const int64_t target = std::max<int64_t>(1, 2048 / k.NW);
     int64_t ntx = std::max<int64_t>(1, (target + tiles - 1) / tiles);
     int lx = (int)((d.nx + ntx - 1) / ntx);
     lx = std::max(lx, 4 * k.T * k.M);
@@ -391,11 +394,13 @@ bool grid_iso(const Dims &d);
 KernelKey default_key(const Dims &d, int T)
 {
     const bool iso = grid_iso(d);
-    // measured on MI355X: small-PY tiles win for T = 1, a tall (2 rows x 16
-    // waves) tile for T >= 2; fall back to whatever is compiled
-    static const int pref1[][2] = {{4, 4}, {4, 8}, {8, 4}};
+    // measured on MI355X: T = 1 wins with 4 rows per thread, in 8 waves for
+    // M <= 4 and 4 waves for longer stencils (register queues of 2M + 1 planes);
+    // a tall (2 rows x 16 waves) tile for T >= 2; fall back to what is compiled
+    static const int pref1s[][2] = {{4, 8}, {4, 4}, {8, 4}};
+    static const int pref1l[][2] = {{4, 4}, {4, 8}, {8, 4}};
     static const int pref2[][2] = {{2, 16}, {4, 8}, {8, 4}};
-    for (auto &sh : (T == 1 ? pref1 : pref2)) {
+    for (auto &sh : (T == 1 ? (d.M <= 4 ? pref1s : pref1l) : pref2)) {
         KernelKey k{d.M, T, sh[0], sh[1], kPlain};
         if (stream_has(k, iso)) return k;
     }
@@ -407,6 +412,9 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
     fd_options eff{};
     if (o) eff = *o;
     if (eff.reserved != 0) return FD_EINVAL;
+    if (eff.flags & ~(uint32_t)(FD_FLAG_NO_CFL_CHECK | FD_FLAG_CHECK_FINITE | FD_FLAG_NO_XCD_REMAP |
+                                FD_FLAG_NO_X_ALTERNATE))
+        return FD_EINVAL;
     if (eff.variant == FD_VARIANT_AUTO) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
@@ -422,6 +430,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         }
     }
     p.remap = !(eff.flags & FD_FLAG_NO_XCD_REMAP);
+    p.alt = !(eff.flags & FD_FLAG_NO_X_ALTERNATE);
     p.variant = eff.variant;
     if (eff.variant == FD_VARIANT_NAIVE) {
         p.key = KernelKey{d.M, 1, 1, 1, kPlain};
@@ -662,7 +671,6 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     a.rscale = 1.0f;
     a.adir = 1;
     a.rdir = 1;
-    a.remap = c.plan.remap ? 1 : 0;
     FDW_HIP(launch_entry_x(a.inj, d.nx, c.L.src.xe, c.s));
     FDW_HIP(launch_entry_x(a.rec, d.nx, c.L.rec.xe, c.s));
     FDW_HIP(launch_scales(a, a.inj, c.L.src.scale, inj_alpha, c.s));
@@ -694,6 +702,41 @@ struct StepOpts {
     int64_t dslot_first = 0; // d2 slot of the first step in the range
     int ddir = 1;
 };
+
+// Super-tile of the XCD-aware tile order (see SweepArgs::remap): gx x-chunks by
+// gy y-tiles by all z-tiles, with a multiple of 8 super-tiles.  Among the
+// admissible shapes, pick the one whose faces to other XCDs re-read the least
+// of u per tile: a y face costs M rows of the (RZ + 2M)-wide halo ring against
+// RY x RZ owned points, an x face costs T M warm-up planes against lx planes.
+// Without an admissible shape the hardware order is kept.
+void supertile(const KernelKey &k, SweepArgs &a)
+{
+    a.gx = a.gy = 1;
+    if (!a.remap) return;
+    const double RY = k.NW * k.PY, RZ = 64.0;
+    double best = 1e300;
+    int bgx = 0, bgy = 0;
+    for (int gx = 1; gx <= a.ntx; ++gx) {
+        if (a.ntx % gx) continue;
+        for (int gy = 1; gy <= a.nty; ++gy) {
+            if (a.nty % gy || ((a.ntx / gx) * (a.nty / gy)) % 8) continue;
+            const double cy = (gy == a.nty) ? 0.0 : 2.0 / gy * k.M * (RZ + 2 * k.M) / (RY * RZ);
+            const double cx = (gx == a.ntx) ? 0.0 : 2.0 / gx * (double)(k.T * k.M) / a.lx;
+            const double cost = cy + cx;
+            if (cost < best - 1e-12 || (cost < best + 1e-12 && gx > bgx)) {
+                best = cost;
+                bgx = gx;
+                bgy = gy;
+            }
+        }
+    }
+    if (!bgx) {
+        a.remap = 0;
+        return;
+    }
+    a.gx = bgx;
+    a.gy = bgy;
+}
 
 // Advance `nsteps` steps, the first one being global step index `step0`.
 void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &so)
@@ -750,6 +793,9 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.ntz = (d.nz + tz - 1) / tz;
         a.nty = (d.ny + ty - 1) / ty;
         a.ntx = (d.nx + a.lx - 1) / a.lx;
+        a.remap = c.plan.remap ? 1 : 0;
+        a.alt = c.plan.alt ? 1 : 0;
+        supertile(k, a);
         c.ex.pass(k, a);
         if (Tk == 1) swap_in(st, o1, st.cur);
         else swap_in(st, o1, o2);
@@ -1245,7 +1291,7 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
         out.push_back(c);
     };
     if (fixed.variant == 0 || fixed.variant == FD_VARIANT_NAIVE) push(FD_VARIANT_NAIVE, 0, 0, 0, 1);
-    static const int shapes[][2] = {{8, 4}, {4, 4}, {16, 2}, {8, 2}, {4, 8}};
+    static const int shapes[][2] = {{4, 8}, {4, 4}, {2, 16}, {8, 4}, {16, 2}, {8, 2}};
     for (int T = 1; T <= 4; ++T) {
         const int variant = T == 1 ? FD_VARIANT_STREAM : FD_VARIANT_TBLOCK;
         if (fixed.variant && fixed.variant != variant) continue;
@@ -1254,10 +1300,12 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
             KernelKey k{d.M, T, sh[0], sh[1], kPlain};
             if (!stream_has(k, grid_iso(d))) continue;
             const int lx0 = default_lx(d, k);
-            for (int f : {1, 2}) {
-                const int lx = std::min(d.nx, std::max(4 * T * d.M, lx0 * f));
+            int last = -1;
+            for (int f : {1, 2, 4, 8}) {  // lx0 / 2, lx0, 2 lx0, 4 lx0
+                const int lx = std::min(std::min(d.nx, kMaxLx), std::max(4 * T * d.M, lx0 * f / 2));
+                if (lx == last) continue;
+                last = lx;
                 push(variant, lx, sh[0] * sh[1], sh[0], T);
-                if (lx == d.nx) break;
             }
         }
     }
@@ -1342,7 +1390,6 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
             Plan p;
             if (make_plan(d, &cand.o, p) != FD_OK) continue;
             c.plan = p;
-            c.base.remap = p.remap ? 1 : 0;
             State st{c.L.fields[2], c.L.fields[3], {c.L.fields[0], c.L.fields[1], nullptr}, 2};
             FDW_HIP(launch_zero(st.cur, d.N * 4, s));
             FDW_HIP(launch_zero(st.prev, d.N * 4, s));
@@ -1446,7 +1493,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
                 done[q] = true;
                 GroupEntry e{};
                 e.a = o.a;
-                e.a.remap = 0;
+                e.a.remap = 0;  // tiles of a grouped launch are in flat order
                 e.tile0 = L.total;
                 L.total += o.a.ntz * o.a.nty * o.a.ntx;
                 host.push_back(e);

@@ -72,10 +72,28 @@ struct SweepArgs {
     // tiling of the launch
     int lx;           // planes per workgroup along x
     int ntz, nty, ntx;
-    int remap;        // XCD-aware tile order
+    // XCD-aware tile order: workgroup b runs on XCD b % 8; with remap != 0 the
+    // tiles are cut into super-tiles of all ntz x gy x gx tiles, dealt to the
+    // XCDs round-robin, so that neighbouring tiles share one XCD's L2.
+    int remap;
+    int gx, gy;
+    // alt != 0: workgroups of odd x-chunks stream x downward, so the planes two
+    // neighbouring chunks both read are read at the same time (both at the
+    // chunks' ends or both at their starts).
+    int alt;
 };
 
 enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
+
+// The damped update's division u = num / (1 + eta), taken only where eta != 0
+// (the sponge), as num times the hardware reciprocal of 1 + eta (v_rcp_f32,
+// within 1 ulp; 1 + eta >= 1, so no denormal can occur).  Every kernel calls
+// this one helper, so all variants round identically; it replaces the
+// ten-instruction IEEE division sequence.
+__device__ __forceinline__ float damped(float num, float eta)
+{
+    return (eta != 0.0f) ? num * __builtin_amdgcn_rcpf(1.0f + eta) : num;
+}
 
 // One shot's pass in a grouped launch: its arguments and the index of its
 // first tile in the launch's flat tile range (entries sorted by tile0).

@@ -15,7 +15,7 @@
 // with s_a = u(-k e_a) + u(+k e_a) (an absent axis contributes +0).
 //   eta = q * (px[x] + (py[y] + pz[z]))
 //   num = fma(q, lap, fma(eta - 1, u_prev, 2 u_c))
-//   u_new = (eta != 0) ? num / (1 + eta) : num          (IEEE division)
+//   u_new = (eta != 0) ? num * rcp(1 + eta) : num       (damped(): hardware reciprocal)
 // then, per source entry at the point in table order: u_new = fma(scale, w, u_new).
 #include "fd_internal.h"
 
@@ -52,9 +52,7 @@ __global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
     const float qv = a.q[c];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
     const float num = fmaf(qv, lap, fmaf(eta - 1.0f, a.um[c], 2.0f * uc));
-    float up = num;
-    if (eta != 0.0f) up = num / (1.0f + eta);
-    a.o1[c] = up;
+    a.o1[c] = damped(num, eta);
 }
 
 hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s)
@@ -234,9 +232,7 @@ __global__ void k_scales(SweepArgs a, PointTable t, float *scale, float alpha)
     const int z = t.yz[j] - y * a.nz;
     const float qv = a.q[(int64_t)x * a.sxy + t.yz[j]];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
-    float base = qv;
-    if (eta != 0.0f) base = qv / (1.0f + eta);
-    scale[j] = alpha * base;
+    scale[j] = alpha * damped(qv, eta);
 }
 
 hipError_t launch_scales(const SweepArgs &a, const PointTable &t, float *scale, float alpha,

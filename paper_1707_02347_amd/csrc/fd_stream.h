@@ -55,11 +55,6 @@ struct Geo {
     static_assert(TY >= 1 && TZ >= 1, "core tile must be non-empty");
 };
 
-__device__ __forceinline__ float ld(const float *base, uint32_t byte_off)
-{
-    return *(const float *)((const char *)base + byte_off);
-}
-
 constexpr uint32_t kOutside = 0x80000000u;  // byte offset of a point outside the grid
 
 // Buffer resource over plane `plane` of a field (an empty range if !valid).
@@ -76,34 +71,68 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t byte_o
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
 }
 
-__device__ __forceinline__ float *at(float *base, uint32_t byte_off)
+// Buffer store: dropped by the hardware when byte_off is beyond the resource's
+// range, so a store for a point outside the output needs no branch.
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v)
 {
-    return (float *)((char *)base + byte_off);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)byte_off, 0, 0);
+}
+
+// Resource over `nbytes` bytes at `base` (an empty range if !valid).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, int64_t nbytes,
+                                                            bool valid)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                             valid ? (int)(uint32_t)nbytes : 0, 0x00020000);
+}
+
+__device__ __forceinline__ double bload64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+
+__device__ __forceinline__ void bstore64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, double v)
+{
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)byte_off, 0, 0);
 }
 
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
 struct StreamKernel {
     using G = Geo<M, T, PY, NW>;
-    // Register queues along x: for short queues the x loop is unrolled by the
-    // queue length Q and the queues rotate by renaming (slot of logical entry j
-    // at phase PH is (PH + 1 + j) mod Q); long queues (M > 4) shift instead, to
-    // keep the loop body small enough for the instruction cache.
+    // Global loads are issued ahead through NS register slots: iteration i
+    // consumes slot i mod NS and, at its start, refills slot (i + NS - 1) mod NS
+    // (consumed in iteration i - 1) with the loads of iteration i + NS - 1.
+    // Every load and store of the loop is issued unconditionally (a point or
+    // plane outside the range gets an offset or resource that the hardware
+    // range check discards), so the compiler can count outstanding memory
+    // operations exactly and never drains the loads still in flight.
+    // For M > 4 a single slot is copied each iteration (one iteration ahead):
+    // more slots would cost a wave per SIMD.
+    static constexpr int NS = (M <= 4) ? 2 : 1;
+    // Register queues along x: for short queues the x loop is unrolled by QS
+    // (the queue length 2M + 1 rounded up to a multiple of NS, so that the
+    // slot of each load is a compile-time constant in every phase) and the
+    // queues rotate by renaming: the slot of logical entry j (0 = oldest,
+    // 2M = newest) at phase PH is (PH - 2M + j) mod QS.  Long queues (M > 4)
+    // shift instead, to keep the loop body small enough for the instruction
+    // cache.
     static constexpr int Q = G::Q;
-    static constexpr bool ROT = (Q <= 9);
-    static constexpr int UNROLL = ROT ? Q : 1;
-    // prefetch depth in planes: two for short stencils; one for M > 4, where the
-    // extra registers would cost a wave per SIMD
-    static constexpr int PD = (M <= 4) ? 2 : 1;
+    static constexpr int QR = (Q + NS - 1) / NS * NS;
+    static constexpr bool ROT = (QR <= 10);
+    static constexpr int QS = ROT ? QR : Q;
+    static constexpr int UNROLL = ROT ? QR : 1;
+    static_assert(UNROLL % NS == 0, "prefetch slots must be compile-time constants");
     // slot of logical queue entry j at phase PH, after / before this phase's push
     template <int PH>
     __device__ static constexpr int pj(int j)
     {
-        return ROT ? (PH + 1 + j) % Q : j;
+        return ROT ? (PH - 2 * M + j + 2 * QS) % QS : j;
     }
     template <int PH>
     __device__ static constexpr int pjb(int j)
     {
-        return ROT ? (PH + j) % Q : j;
+        return ROT ? (PH - 1 - 2 * M + j + 2 * QS) % QS : j;
     }
 
     // Level-0 plane with its M-wide halo ring; planes of levels 1..T-1 over the
@@ -126,7 +155,8 @@ struct StreamKernel {
     };
 
     struct Thread {
-        int lane, wv, x0, xend, cbase;
+        int lane, wv, x0, xend, cbase, iend;
+        int refl;           // -1: stream upward; else plane of position i is refl - i
         uint32_t bo[PY];    // byte offset of each owned point in a plane (kOutside if outside)
         bool din[PY];       // owned point inside the grid
         bool core[PY];      // owned point inside the output tile
@@ -138,21 +168,37 @@ struct StreamKernel {
     // Run tile `bid` of the ntiles tiles of one shot's pass.
     __device__ static void run(const SweepArgs &a, Smem &sm, int bid, int ntiles)
     {
-        // -------- tile decode (optionally XCD-aware: consecutive tiles on one XCD)
-        if (a.remap && (ntiles & 7) == 0) {
-            const int per = ntiles >> 3;
-            bid = (bid & 7) * per + (bid >> 3);
+        // -------- tile decode
+        int bz, by, bx;
+        if (a.remap) {
+            // slot s of XCD k (workgroups are dealt to the 8 XCDs round-robin)
+            // runs tile s of that XCD's super-tiles k, k + 8, ...; a super-tile
+            // is all ntz z-tiles of gy consecutive y-tiles and gx x-chunks, z
+            // fastest, so the tiles of one super-tile start together
+            const int xcd = bid & 7, slot = bid >> 3;
+            const int tps = a.ntz * a.gy * a.gx;
+            const int sup = (slot / tps) * 8 + xcd;
+            const int loc = slot % tps;
+            const int nsy = a.nty / a.gy;
+            bz = loc % a.ntz;
+            by = (sup % nsy) * a.gy + (loc / a.ntz) % a.gy;
+            bx = (sup / nsy) * a.gx + loc / (a.ntz * a.gy);
+        } else {
+            bz = bid % a.ntz;
+            by = (bid / a.ntz) % a.nty;
+            bx = bid / (a.ntz * a.nty);
         }
-        const int bz = bid % a.ntz;
-        const int rest = bid / a.ntz;
-        const int by = rest % a.nty;
-        const int bx = rest / a.nty;
         const int z1 = bz * G::TZ - G::H1;
         const int y1 = by * G::TY - G::H1;
 
         Thread th;
         th.x0 = bx * a.lx;
         th.xend = min(th.x0 + a.lx, a.nx);
+        // stream position i maps to plane i (upward) or x0 + xend - 1 - i
+        // (downward); the set of planes a chunk touches is symmetric under
+        // that reflection, so both directions visit the same planes, and the
+        // x stencil is symmetric, so the results are the same bits
+        th.refl = (a.alt && (bx & 1)) ? th.x0 + th.xend - 1 : -1;
         th.cbase = th.x0 - (T - 1) * M;
         th.lane = threadIdx.x & 63;
         th.wv = threadIdx.x >> 6;
@@ -190,13 +236,13 @@ struct StreamKernel {
         }
         // (the first barrier of the loop orders these writes before any read)
 
-        float qu[T][PY][G::Q];  // level t's queue of u^{t-1}: planes c_t - M .. c_t + M
+        float qu[T][PY][QS];  // level t's queue of u^{t-1}: planes c_t - M .. c_t + M
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
             for (int r = 0; r < PY; ++r)
 #pragma unroll
-                for (int j = 0; j < G::Q; ++j) qu[t][r][j] = 0.0f;
+                for (int j = 0; j < QS; ++j) qu[t][r][j] = 0.0f;
 
         double acc[(MODE == kImaging) ? PY : 1][(MODE == kImaging) ? G::AQ : 1];
         if constexpr (MODE == kImaging) {
@@ -207,13 +253,13 @@ struct StreamKernel {
         }
 
         const int ibeg = th.x0 - T * M;
-        const int iend = th.xend + T * M;
+        th.iend = th.xend + T * M;
         const int64_t N = (int64_t)a.nx * a.sxy;
 
-        Pre pf[PD];  // pf[d] holds the loads of iteration i + d
+        Pre pf[NS];  // slot (i - ibeg) mod NS holds the loads of iteration i
 #pragma unroll
-        for (int d = 0; d < PD; ++d) load(a, th, pf[d], ibeg + d);
-        for (int i0 = ibeg; i0 < iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, iend, N);
+        for (int d = 0; d < ((NS > 1) ? NS - 1 : 1); ++d) load(a, th, pf[d], ibeg + d);
+        for (int i0 = ibeg; i0 < th.iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, N);
     }
 
     // Iterations i0 + PH .. i0 + UNROLL - 1 of the x loop (one per phase).  Each
@@ -222,17 +268,32 @@ struct StreamKernel {
     // barrier per iteration serves every level.
     template <int PH, class QU, class ACC>
     __device__ static __forceinline__ void block(const SweepArgs &a, Smem &sm, const Thread &th,
-                                                 QU &qu, ACC &acc, Pre (&pf)[PD], int i0, int iend,
-                                                 int64_t N)
+                                                 QU &qu, ACC &acc, Pre (&pf)[NS], int i0, int64_t N)
     {
         if constexpr (PH < UNROLL) {
             const int i = i0 + PH;
-            if (i < iend) {
+            if (i < th.iend) {
+                if constexpr (NS == 1) {
+                    const Pre cur = pf[0];
+                    load(a, th, pf[0], i + 1);
+                    step<PH>(a, sm, th, qu, acc, cur, i, N);
+                } else {
+                    load(a, th, pf[(PH + NS - 1) % NS], i + NS - 1);
+                    step<PH>(a, sm, th, qu, acc, pf[PH % NS], i, N);
+                }
+                block<PH + 1>(a, sm, th, qu, acc, pf, i0, N);
+            }
+        }
+    }
+
+    // One iteration: publish, barrier, the T levels.
+    template <int PH, class QU, class ACC>
+    __device__ static __forceinline__ void step(const SweepArgs &a, Smem &sm, const Thread &th,
+                                                QU &qu, ACC &acc, const Pre &cur, int i, int64_t N)
+    {
+        {
+            {
                 const int par = i & 1;
-                const Pre cur = pf[0];
-#pragma unroll
-                for (int d = 0; d + 1 < PD; ++d) pf[d] = pf[d + 1];
-                if (i + PD < iend) load(a, th, pf[PD - 1], i + PD);
                 if constexpr (MODE == kImaging) {
 #pragma unroll
                     for (int r = 0; r < PY; ++r)
@@ -245,7 +306,6 @@ struct StreamKernel {
 #pragma unroll
                 for (int r = 0; r < PY; ++r) val[r] = cur.head[r];
                 level<1, PH>(a, sm, th, qu, acc, val, cur, i, par, N);
-                block<PH + 1>(a, sm, th, qu, acc, pf, i0, iend, N);
             }
         }
     }
@@ -293,6 +353,20 @@ struct StreamKernel {
         return h < G::NHALO;
     }
 
+    // Offset of owned point r for output stores: beyond the plane unless the
+    // point is inside the output tile (computed per use: a register per row
+    // held for the whole pass costs occupancy at M = 8).
+    __device__ static __forceinline__ uint32_t out_off(const Thread &th, int r)
+    {
+        return th.core[r] ? th.bo[r] : kOutside;
+    }
+
+    // Plane at stream position i.
+    __device__ static __forceinline__ int plane(const Thread &th, int i)
+    {
+        return th.refl < 0 ? i : th.refl - i;
+    }
+
     // Planes level t must produce: [x0 - (T - t) M, xend + (T - t) M) within the grid.
     __device__ static __forceinline__ bool needed(const SweepArgs &a, const Thread &th, int t, int c)
     {
@@ -304,10 +378,11 @@ struct StreamKernel {
     // u^{n-1} at plane i - M; q at every level's plane i - t M.
     __device__ static __forceinline__ void load(const SweepArgs &a, const Thread &th, Pre &P, int i)
     {
-        const auto rh = plane_rsrc(a.u0, i, a.sxy, (unsigned)i < (unsigned)a.nx);
+        const int ph = plane(th, i);
+        const auto rh = plane_rsrc(a.u0, ph, a.sxy, (unsigned)ph < (unsigned)a.nx && i < th.iend);
 #pragma unroll
         for (int r = 0; r < PY; ++r) P.head[r] = bload(rh, th.bo[r]);
-        const int c1 = i - M;
+        const int c1 = plane(th, i - M);
         const bool l1 = needed(a, th, 1, c1);
         const auto rc = plane_rsrc(a.u0, c1, a.sxy, l1);
 #pragma unroll
@@ -317,7 +392,7 @@ struct StreamKernel {
         for (int r = 0; r < PY; ++r) P.up1[r] = bload(rm, th.bo[r]);
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
-            const int ct = i - t * M;
+            const int ct = plane(th, i - t * M);
             const auto rq = plane_rsrc(a.q, ct, a.sxy, needed(a, th, t, ct));
 #pragma unroll
             for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload(rq, th.bo[r]);
@@ -330,13 +405,13 @@ struct StreamKernel {
                                                  QU &qu, ACC &acc, float (&val)[PY], const Pre &P,
                                                  int i, int par, int64_t N)
     {
-        const int c = i - t * M;
+        const int c = plane(th, i - t * M);
         const int lane = th.lane, wv = th.wv;
         // push the newest plane (c + M) into level t's queue
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
             if constexpr (ROT) {
-                qu[t - 1][r][PH] = val[r];  // the slot of the oldest entry
+                qu[t - 1][r][PH] = val[r];  // newest entry; the slot held one no longer used
             } else {
 #pragma unroll
                 for (int j = 0; j + 1 < Q; ++j) qu[t - 1][r][j] = qu[t - 1][r][j + 1];
@@ -397,9 +472,7 @@ struct StreamKernel {
                 else up = qu[t - 2][r][pj<PH>(0)];
                 const float eta = qv * (pxv + th.pyz[r]);
                 const float num = fmaf(qv, lap, fmaf(eta - 1.0f, up, 2.0f * uc));
-                float o = num;
-                if (eta != 0.0f) o = num / (1.0f + eta);
-                out[r] = active ? o : 0.0f;
+                out[r] = active ? damped(num, eta) : 0.0f;
             }
             const int step = a.step0 + t - 1;
             {
@@ -420,8 +493,7 @@ struct StreamKernel {
                     }
                 }
             }
-            const bool own = c >= th.x0 && c < th.xend;
-            if (own) {
+            if (c >= th.x0 && c < th.xend) {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.rxp[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.rxp[tj + 1]);
                 if (jb < je) {
@@ -434,59 +506,57 @@ struct StreamKernel {
                     }
                 }
             }
-            if constexpr (MODE == kSaveD2) {
-                if (own) {
-                    float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N +
-                                (int64_t)c * a.sxy;
-#pragma unroll
-                    for (int r = 0; r < PY; ++r) {
-                        if (th.core[r]) {
-                            float um;
-                            if constexpr (t == 1) um = P.up1[r];
-                            else um = qu[t - 2][r][pj<PH>(0)];
-                            *at(dp, th.bo[r]) = fmaf(-2.0f, qu[t - 1][r][pj<PH>(M)], out[r]) + um;
-                        }
-                    }
-                }
-            }
-            if constexpr (MODE == kImaging) {
-                if (own) {
-                    const float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N +
-                                      (int64_t)c * a.sxy;
-                    double *gp = a.g + (int64_t)c * a.sxy;
-                    constexpr int J = (T - t) * M;
-#pragma unroll
-                    for (int r = 0; r < PY; ++r) {
-                        if (th.core[r]) {
-                            const uint32_t e = th.bo[r] >> 2;
-                            double base;
-                            if constexpr (t == 1) base = gp[e];
-                            else base = acc[r][J];
-                            const double nv = fma((double)out[r], (double)ld(dp, th.bo[r]), base);
-                            if constexpr (t == T) gp[e] = nv;
-                            else acc[r][J] = nv;
-                        }
-                    }
-                }
-            }
         } else {
 #pragma unroll
             for (int r = 0; r < PY; ++r) out[r] = 0.0f;
         }
+        // gradient support (outside the branch above, so that every memory
+        // operation of the iteration is issued unconditionally; own planes are
+        // always needed)
+        const bool own = c >= th.x0 && c < th.xend;
+        if constexpr (MODE == kSaveD2) {
+            const float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N +
+                              (int64_t)(own ? c : 0) * a.sxy;
+            const auto rd = span_rsrc(dp, a.sxy * 4, own);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                float um;
+                if constexpr (t == 1) um = P.up1[r];
+                else um = qu[t - 2][r][pj<PH>(0)];
+                bstore(rd, out_off(th, r), fmaf(-2.0f, qu[t - 1][r][pj<PH>(M)], out[r]) + um);
+            }
+        }
+        if constexpr (MODE == kImaging) {
+            // points outside the output tile read 0 and are not stored; the
+            // FP64 accumulator plane is addressed with offsets 2 bo (the
+            // planner keeps ny nz < 2^28 for gradients, so 2 bo < 2^31)
+            const int64_t cp = (int64_t)(own ? c : 0) * a.sxy;
+            const float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N + cp;
+            const auto rd = span_rsrc(dp, a.sxy * 4, own);
+            const auto rg = span_rsrc(a.g + cp, a.sxy * 8, own);
+            constexpr int J = (T - t) * M;
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                const uint32_t og = th.core[r] ? 2u * th.bo[r] : kOutside;
+                double base;
+                if constexpr (t == 1) base = bload64(rg, og);
+                else base = acc[r][J];
+                const double nv = fma((double)out[r], (double)bload(rd, out_off(th, r)), base);
+                if constexpr (t == T) bstore64(rg, og, nv);
+                else acc[r][J] = nv;
+            }
+        }
 
         if constexpr (t == T) {
             // the pass's outputs at plane c: u^{n+T} and (T >= 2) u^{n+T-1}
-            if (xin && c >= th.x0 && c < th.xend) {
-                float *o1 = a.o1 + (int64_t)c * a.sxy;
+            const bool outp = xin && own;
+            const auto r1 = plane_rsrc(a.o1, c, a.sxy, outp);
 #pragma unroll
-                for (int r = 0; r < PY; ++r)
-                    if (th.core[r]) *at(o1, th.bo[r]) = out[r];
-                if constexpr (T >= 2) {
-                    float *o2 = a.o2 + (int64_t)c * a.sxy;
+            for (int r = 0; r < PY; ++r) bstore(r1, out_off(th, r), out[r]);
+            if constexpr (T >= 2) {
+                const auto r2 = plane_rsrc(a.o2, c, a.sxy, outp);
 #pragma unroll
-                    for (int r = 0; r < PY; ++r)
-                        if (th.core[r]) *at(o2, th.bo[r]) = qu[T - 1][r][pj<PH>(M)];
-                }
+                for (int r = 0; r < PY; ++r) bstore(r2, out_off(th, r), qu[T - 1][r][pj<PH>(M)]);
             }
         } else {
 #pragma unroll

@@ -142,6 +142,8 @@ def test_unsupported_tile_is_reported():
     assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EUNSUPPORTED
     o = L.make_options(variant=9)
     assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
+    o = L.make_options(flags=1 << 7)  # not an FD_FLAG_*
+    assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
 
 
 def test_gradient_and_adjoint_validate_on_host():
