@@ -460,17 +460,21 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
     return FD_OK;
 }
 
-// Key with the same tile for another mode / depth, falling back to T = 1 (8, 4).
+// Key with the same tile for another mode / depth; otherwise the first compiled
+// shape of a preference list at depth T, then at depth 1.
 KernelKey key_for(const KernelKey &base, int T, int mode, bool iso)
 {
     KernelKey k = base;
     k.T = T;
     k.mode = mode;
     if (stream_has(k, iso)) return k;
-    k = KernelKey{base.M, T, 8, 4, mode};
-    if (stream_has(k, iso)) return k;
-    k = KernelKey{base.M, T, 4, 8, mode};
-    if (stream_has(k, iso)) return k;
+    static const int shapes[][2] = {{4, 8}, {2, 16}, {4, 4}, {8, 4}};
+    for (int t : {T, 1}) {
+        for (auto &sh : shapes) {
+            k = KernelKey{base.M, t, sh[0], sh[1], mode};
+            if (stream_has(k, iso)) return k;
+        }
+    }
     return KernelKey{base.M, 1, 8, 4, mode};
 }
 

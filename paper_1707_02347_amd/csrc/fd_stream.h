@@ -100,6 +100,14 @@ __device__ __forceinline__ void bstore64(__amdgpu_buffer_rsrc_t r, uint32_t byte
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
 struct StreamKernel {
     using G = Geo<M, T, PY, NW>;
+    // Register queues along x.  Short queues (M <= 4) rotate by renaming: the
+    // x loop is unrolled by QS (the queue length 2M + 1 rounded up to a
+    // multiple of NS below) and the slot of logical entry j (0 = oldest,
+    // 2M = newest) at phase PH is (PH - 2M + j) mod QS.  Long queues (M > 4)
+    // shift instead, to keep the loop body small enough for the instruction
+    // cache; so do the time-blocked gradient modes, whose unrolled bodies
+    // would not fit in the register file.
+    static constexpr bool ROT = (M <= 4) && !(T >= 2 && MODE != kPlain);
     // Global loads are issued ahead through NS register slots: iteration i
     // consumes slot i mod NS and, at its start, refills slot (i + NS - 1) mod NS
     // (consumed in iteration i - 1) with the loads of iteration i + NS - 1.
@@ -107,21 +115,12 @@ struct StreamKernel {
     // plane outside the range gets an offset or resource that the hardware
     // range check discards), so the compiler can count outstanding memory
     // operations exactly and never drains the loads still in flight.
-    // For M > 4 a single slot is copied each iteration (one iteration ahead):
-    // more slots would cost a wave per SIMD.
-    static constexpr int NS = (M <= 4) ? 2 : 1;
-    // Register queues along x: for short queues the x loop is unrolled by QS
-    // (the queue length 2M + 1 rounded up to a multiple of NS, so that the
-    // slot of each load is a compile-time constant in every phase) and the
-    // queues rotate by renaming: the slot of logical entry j (0 = oldest,
-    // 2M = newest) at phase PH is (PH - 2M + j) mod QS.  Long queues (M > 4)
-    // shift instead, to keep the loop body small enough for the instruction
-    // cache.
+    // Without rotation a single slot is copied each iteration (one iteration
+    // ahead as well).
+    static constexpr int NS = ROT ? 2 : 1;
     static constexpr int Q = G::Q;
-    static constexpr int QR = (Q + NS - 1) / NS * NS;
-    static constexpr bool ROT = (QR <= 10);
-    static constexpr int QS = ROT ? QR : Q;
-    static constexpr int UNROLL = ROT ? QR : 1;
+    static constexpr int QS = (Q + NS - 1) / NS * NS;
+    static constexpr int UNROLL = ROT ? QS : 1;
     static_assert(UNROLL % NS == 0, "prefetch slots must be compile-time constants");
     // slot of logical queue entry j at phase PH, after / before this phase's push
     template <int PH>
@@ -147,11 +146,16 @@ struct StreamKernel {
         int rxp[G::SPAN];
     };
 
+    static constexpr bool IMG = (MODE == kImaging);
     struct Pre {
         float head[PY];
         float halo[G::HS];
         float up1[PY];
         float q[T][PY];
+        // imaging: the FP64 accumulator at level 1's plane and the saved second
+        // differences at every level's plane
+        double g[IMG ? PY : 1];
+        float d2[IMG ? T : 1][IMG ? PY : 1];
     };
 
     struct Thread {
@@ -360,6 +364,12 @@ struct StreamKernel {
     {
         return th.core[r] ? th.bo[r] : kOutside;
     }
+    // The same for the FP64 accumulator plane (8-byte elements; the planner
+    // keeps ny nz < 2^28, so 2 bo < 2^31).
+    __device__ static __forceinline__ uint32_t out_off64(const Thread &th, int r)
+    {
+        return th.core[r] ? 2u * th.bo[r] : kOutside;
+    }
 
     // Plane at stream position i.
     __device__ static __forceinline__ int plane(const Thread &th, int i)
@@ -396,6 +406,25 @@ struct StreamKernel {
             const auto rq = plane_rsrc(a.q, ct, a.sxy, needed(a, th, t, ct));
 #pragma unroll
             for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload(rq, th.bo[r]);
+        }
+        if constexpr (IMG) {
+            // only planes this chunk owns are read (and later written); offsets
+            // of points outside the output tile are beyond the plane
+            const bool o1 = c1 >= th.x0 && c1 < th.xend;
+            const auto rg = span_rsrc(a.g + (int64_t)(o1 ? c1 : 0) * a.sxy, a.sxy * 8, o1);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) P.g[r] = bload64(rg, out_off64(th, r));
+            const int64_t N = (int64_t)a.nx * a.sxy;
+#pragma unroll
+            for (int t = 1; t <= T; ++t) {
+                const int ct = plane(th, i - t * M);
+                const bool ot = ct >= th.x0 && ct < th.xend;
+                const float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N +
+                                  (int64_t)(ot ? ct : 0) * a.sxy;
+                const auto rd = span_rsrc(dp, a.sxy * 4, ot);
+#pragma unroll
+                for (int r = 0; r < PY; ++r) P.d2[t - 1][r] = bload(rd, out_off(th, r));
+            }
         }
     }
 
@@ -527,22 +556,17 @@ struct StreamKernel {
             }
         }
         if constexpr (MODE == kImaging) {
-            // points outside the output tile read 0 and are not stored; the
-            // FP64 accumulator plane is addressed with offsets 2 bo (the
-            // planner keeps ny nz < 2^28 for gradients, so 2 bo < 2^31)
-            const int64_t cp = (int64_t)(own ? c : 0) * a.sxy;
-            const float *dp = a.d2 + (a.dslot0 + (int64_t)a.ddir * (t - 1)) * N + cp;
-            const auto rd = span_rsrc(dp, a.sxy * 4, own);
-            const auto rg = span_rsrc(a.g + cp, a.sxy * 8, own);
+            // g (level 1's plane) and d2 were loaded with this iteration's other
+            // inputs; points outside the output tile read 0 and are not stored
+            const auto rg = span_rsrc(a.g + (int64_t)(own ? c : 0) * a.sxy, a.sxy * 8, own);
             constexpr int J = (T - t) * M;
 #pragma unroll
             for (int r = 0; r < PY; ++r) {
-                const uint32_t og = th.core[r] ? 2u * th.bo[r] : kOutside;
                 double base;
-                if constexpr (t == 1) base = bload64(rg, og);
+                if constexpr (t == 1) base = P.g[r];
                 else base = acc[r][J];
-                const double nv = fma((double)out[r], (double)bload(rd, out_off(th, r)), base);
-                if constexpr (t == T) bstore64(rg, og, nv);
+                const double nv = fma((double)out[r], (double)P.d2[t - 1][r], base);
+                if constexpr (t == T) bstore64(rg, out_off64(th, r), nv);
                 else acc[r][J] = nv;
             }
         }
