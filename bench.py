@@ -208,6 +208,43 @@ def oracle_baseline(cs, budget_s=20.0):
             "seconds": round(t, 3)}
 
 
+# Time-blocking study on the HBM-bound 512^3 grid of the so-16 workload: for
+# short stencils the overlap 2M(T-1) is small, so levels of time blocking pay
+# for the redundant halo work by cutting HBM traffic (MI355X sweeps).
+TIME_BLOCKING = {
+    2: (dict(variant=2, tile=(256, 32, 4)), dict(variant=3, tblock=4, tile=(128, 32, 2))),
+    4: (dict(variant=2, tile=(256, 32, 4)), dict(variant=3, tblock=3, tile=(64, 32, 2))),
+    8: (dict(variant=2, tile=(128, 32, 4)), dict(variant=3, tblock=2, tile=(64, 32, 2))),
+}
+
+
+def time_blocking_study(nt=48):
+    """512^3, sponge 40, space orders 2 / 4 / 8: best space-tiled (T = 1) vs best
+    time-blocked configuration, GPts/s over nt steps (sweep minus set-up)."""
+    import torch
+
+    import synth
+
+    base = workload("cfg3")
+    out = {}
+    for so, (o1, o2) in TIME_BLOCKING.items():
+        cs = dict(base)
+        cs["so"] = so
+        cs["nt"] = nt
+        cs["dt"] = 0.8 * courant_max(so, 3) * 10.0 / 4500.0
+        cs["amp"] = torch.from_numpy(synth.ricker(nt, cs["dt"], 15.0)[:, None].copy()).to(base["v"].device)
+        npts = int(np.prod(cs["v"].shape))
+        r = {}
+        for name, o in (("T1", o1), (f"T{o2['tblock']}", o2)):
+            med, _, _ = time_sweeps(cs, o, 3, 1)
+            ms = max(med - setup_ms(cs, o), 1e-6)
+            r[name] = round(npts * nt / (ms * 1e-3) / 1e9, 1)
+        out[f"so{so}"] = r
+    del base
+    torch.cuda.empty_cache()
+    return out
+
+
 def gradient_rate(reps=2, warmup=1):
     """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
     import torch
@@ -388,6 +425,8 @@ def main():
         line["cfg3_bw_equiv_frac_16B"] = round(r3["tiled"] * 16 / HBM_PEAK_GBS, 4)
         del c3
         torch.cuda.empty_cache()
+        print("# time blocking at 512^3", file=sys.stderr, flush=True)
+        line["time_blocking_512cube_gpts"] = time_blocking_study()
         print("# cfg4", file=sys.stderr, flush=True)
         line["cfg4_fwi_gradient"] = gradient_rate()
         print("# cfg5", file=sys.stderr, flush=True)

@@ -601,18 +601,35 @@ __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 }
 
 // Grouped persistent pass: the workgroups walk the flat tile range of all the
-// entries (one per shot) of a batch.
+// entries (one per shot) of a batch.  Workgroup b runs on XCD b % 8; when the
+// grid is a multiple of 8, the items of one round are dealt so that each XCD
+// takes a contiguous block of them (neighbouring tiles of one shot share that
+// XCD's L2).
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
 __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__restrict__ list,
                                                             int nlist, int total)
 {
     using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
     __shared__ typename K::Smem sm;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = blockIdx.x;
+    const int first = ((gridDim.x & 7) == 0) ? (b & 7) * (gridDim.x >> 3) + (b >> 3) : b;
+    // The table is read through the constant address space: it does not change
+    // during the launch, so the compiler may keep the entry's fields in scalar
+    // registers across the whole tile instead of reloading them after every
+    // store of the streaming loop.
+    // (The host pass only sees a stub of this body; it has no constant
+    // address space, so it reads the table directly.)
+#if defined(__HIP_DEVICE_COMPILE__)
+    using CEntry = const __attribute__((address_space(4))) GroupEntry;
+    CEntry *clist = (CEntry *)list;
+#else
+    const GroupEntry *clist = list;
+#endif
+    for (int item = first; item < total; item += gridDim.x) {
         int e = 0;
-        while (e + 1 < nlist && list[e + 1].tile0 <= item) ++e;
-        const SweepArgs &a = list[e].a;
-        K::run(a, sm, item - list[e].tile0, a.ntz * a.nty * a.ntx);
+        while (e + 1 < nlist && clist[e + 1].tile0 <= item) ++e;
+        const SweepArgs a = clist[e].a;
+        K::run(a, sm, item - clist[e].tile0, a.ntz * a.nty * a.ntx);
         __syncthreads();  // the next tile rewrites the LDS tables and planes
     }
 }
@@ -653,21 +670,24 @@ bool entry_launch_group(bool iso, const GroupEntry *list, int nlist, int total, 
     return false;
 }
 
+// Resident workgroups per CU: of the grouped kernel where it is compiled, else
+// of the single-pass kernel (0 if the requested form is not compiled).
 template <int M, int T, int PY, int NW, int MODE, int F>
 int entry_occupancy(bool iso)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
+    const void *fn = nullptr;
     if constexpr ((F & 2) != 0) {
-        if (iso)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &n, reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>),
-                64 * NW, 0);
+        if (iso) fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>);
         else if constexpr ((F & 1) != 0)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &n, reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>),
-                64 * NW, 0);
+            fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>);
+    } else {
+        if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true>);
+        else if constexpr ((F & 1) != 0)
+            fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, false>);
     }
+    if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * NW, 0);
     return e == hipSuccess ? n : 0;
 }
 

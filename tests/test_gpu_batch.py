@@ -16,7 +16,7 @@ DEV = "cuda"
 def make_shots(gradient=False):
     specs = [((40, 38, 44), 4, 30, {}), ((36, 44, 52), 8, 25, {}), ((48, 40, 46), 16, 20, {}),
              ((60, 70), 4, 40, {}), ((44, 40, 50), 8, 27, dict(variant=L.FD_VARIANT_TBLOCK, tblock=2)),
-             ((42, 37, 45), 4, 33, dict(variant=L.FD_VARIANT_TBLOCK, tblock=3, tile=(0, 32, 8)))]
+             ((42, 37, 45), 4, 33, dict(variant=L.FD_VARIANT_TBLOCK, tblock=3, tile=(0, 32, 4)))]
     shots = []
     for i, (shape, so, nt, opts) in enumerate(specs):
         nd = len(shape)

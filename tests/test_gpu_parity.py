@@ -71,12 +71,16 @@ def gpu_forward(cs, u0=None, um1=None, **opts):
 def configs_for(so, small_chunk=7):
     M = so // 2
     out = [dict(variant=L.FD_VARIANT_NAIVE)]
-    shapes = {1: [(32, 8, 1), (16, 4, 1), (32, 16, 1), (32, 8, 2), (32, 8, 3), (32, 8, 4)],
-              2: [(32, 8, 1), (16, 4, 1), (32, 16, 1), (32, 8, 2), (32, 8, 3), (32, 8, 4), (32, 4, 2)],
-              4: [(32, 8, 1), (16, 4, 1), (32, 16, 1), (16, 8, 1), (32, 8, 2), (32, 4, 2), (32, 4, 3),
-                  (32, 4, 1), (32, 2, 1), (16, 2, 1), (32, 2, 2), (64, 4, 2), (32, 2, 3)],
-              8: [(32, 8, 1), (16, 4, 1), (16, 8, 1), (32, 4, 2), (32, 8, 2), (32, 4, 1), (32, 2, 1),
-                  (32, 2, 2), (64, 4, 2)]}.get(M, [(32, 8, 1)])
+    # (tile rows, rows per thread, time levels) of every compiled configuration
+    shapes = {1: [(32, 8, 1), (16, 4, 1), (32, 4, 1), (32, 16, 1), (32, 4, 2), (32, 2, 2), (32, 4, 3),
+                  (32, 2, 3), (32, 4, 4), (32, 2, 4)],
+              2: [(32, 8, 1), (16, 4, 1), (32, 4, 1), (32, 16, 1), (32, 4, 2), (32, 2, 2), (32, 4, 3),
+                  (32, 2, 3), (32, 2, 4)],
+              3: [(32, 8, 1), (32, 4, 1)],
+              4: [(32, 8, 1), (16, 4, 1), (32, 16, 1), (16, 8, 1), (32, 4, 1), (32, 2, 1), (16, 2, 1),
+                  (32, 4, 2), (32, 2, 2), (64, 4, 2), (32, 4, 3), (32, 2, 3)],
+              8: [(32, 8, 1), (16, 4, 1), (16, 8, 1), (32, 4, 1), (32, 2, 1), (32, 4, 2), (32, 2, 2),
+                  (64, 4, 2)]}.get(M, [(32, 8, 1), (16, 4, 1)])
     for rows, py, tb in shapes:
         var = L.FD_VARIANT_STREAM if tb == 1 else L.FD_VARIANT_TBLOCK
         out.append(dict(variant=var, tile=(0, rows, py), tblock=tb))
@@ -136,7 +140,8 @@ def test_paper_gaussian_initial_field_matches_oracle():
 
 # ---------------------------------------------------------------- variants bit-exact
 @pytest.mark.parametrize("shape,so", [((37, 45, 70), 8), ((21, 9, 130), 4), ((30, 33, 65), 2),
-                                      ((40, 38, 80), 16), ((26, 77), 4), ((19, 23, 41), 6)])
+                                      ((40, 38, 80), 16), ((26, 77), 4), ((19, 23, 41), 6),
+                                      ((25, 31, 44), 10)])
 def test_all_configs_bit_identical_to_untiled(shape, so):
     nt = 13
     cs = make_case(shape, so, nt, sponge=3, nsrc=3, nrec=10, depth=shape[-1] // 2)
@@ -295,7 +300,7 @@ def test_vjp_equals_gradient_with_residual_cotangent():
 
 # ---------------------------------------------------------------- state, resume and errors
 @pytest.mark.parametrize("opt", [dict(variant=L.FD_VARIANT_NAIVE), dict(variant=L.FD_VARIANT_STREAM),
-                                 dict(variant=L.FD_VARIANT_TBLOCK, tblock=3, tile=(0, 32, 8))])
+                                 dict(variant=L.FD_VARIANT_TBLOCK, tblock=3, tile=(0, 32, 4))])
 def test_resume_is_bit_exact(opt):
     cs = make_case((40, 42, 66), 4, 60, 5, nsrc=2, nrec=6)
     full = gpu_forward(cs, **opt)
@@ -357,6 +362,6 @@ def test_anisotropic_spacing_matches_oracle_and_variants_agree(so):
     assert rel_l2(base["u"].cpu().numpy(), ref["u"]) <= 1e-5
     for opt in (dict(variant=L.FD_VARIANT_STREAM), dict(variant=L.FD_VARIANT_STREAM, tile=(9, 32, 8)),
                 dict(variant=L.FD_VARIANT_TBLOCK, tblock=2), dict(variant=L.FD_VARIANT_TBLOCK, tblock=2,
-                                                                  tile=(0, 32, 8))):
+                                                                  tile=(0, 32, 4))):
         out = gpu_forward(cs, **opt)
         assert torch.equal(out["u"], base["u"]) and torch.equal(out["rec"], base["rec"]), opt
