@@ -243,7 +243,7 @@ size_t fd_batch_workspace_size(int nshots, const fd_shot *shots, int op);
  * Batched forward sweeps over shots of uneven grid size and space order.
  * All shots' time blocks are issued as grouped launches: one launch per
  * (space order, time-block depth) class per pass covers the tiles of every shot
- * in that class, its workgroups walking the tile table persistently.  With
+ * in that class, each workgroup finding its shot and tile in a device table.  With
  * flags & FD_BATCH_GRAPH the whole sequence is captured once into a hipGraph
  * and replayed.  Synchronises the stream (stability checks and graph build).
  */

@@ -47,16 +47,16 @@ bool launch_stream_grouped(const KernelKey &k, bool iso, const GroupEntry *list,
     return e && e->launch_group(iso, list, nlist, total, grid, s);
 }
 
-int stream_occupancy(const KernelKey &k, bool iso)
+int stream_occupancy(const KernelKey &k, bool iso, bool grouped)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
-    const auto key = std::make_tuple(k.M, k.T, k.PY, k.NW, k.mode, iso ? 1 : 0);
+    static std::map<std::tuple<int, int, int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(k.M, k.T, k.PY, k.NW, k.mode, iso ? 1 : 0, grouped ? 1 : 0);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     const StreamEntry *e = find_entry(k);
-    const int n = e ? e->occupancy(iso) : 0;
+    const int n = e ? e->occupancy(iso, grouped) : 0;
     cache[key] = n;
     return n;
 }
@@ -100,7 +100,9 @@ struct Dims {
     int ndim;
     int M;
     int nx, ny, nz;        // as 3-D
-    int64_t N;
+    int nzp;               // row pitch of the internal fields (nz rounded up to 32 floats)
+    int64_t N;             // points (the caller's dense layout)
+    int64_t Np;            // floats of one internal field: nx ny nzp
     double h[3];           // spacing of the 3-D axes (1 for absent axes)
     bool present[3];
 };
@@ -130,10 +132,15 @@ int make_dims(const fd_grid *g, Dims &d)
     d.ny = (int)n3[1];
     d.nz = (int)n3[2];
     d.N = n3[0] * n3[1] * n3[2];
+    // Internal fields pad each z row to a multiple of 32 floats (128 bytes), so
+    // that a wave's 64 consecutive points always span two whole cache lines;
+    // the caller's arrays stay dense and are converted at the boundary.
+    d.nzp = (int)((n3[2] + 31) / 32 * 32);
+    d.Np = n3[0] * n3[1] * (int64_t)d.nzp;
     // one (y, z) plane must stay below 2^28 points: kernels address a plane
     // with 32-bit byte offsets (8-byte elements for the FP64 imaging
     // accumulator) and mark points outside the grid with offset 2^31
-    if (n3[1] * n3[2] >= ((int64_t)1 << 28)) return FD_EINVAL;
+    if (n3[1] * (int64_t)d.nzp >= ((int64_t)1 << 28)) return FD_EINVAL;
     for (int a = 0; a < 3; ++a) {
         d.h[a] = h3[a];
         d.present[a] = p3[a];
@@ -296,19 +303,19 @@ Layout layout(void *ws, const Dims &d, int64_t nt, int ns, int nr, int op, int n
 {
     Carver cv(ws);
     Layout L;
-    L.q = cv.take<float>(d.N);
+    L.q = cv.take<float>(d.Np);
     L.prof = cv.take<float>((size_t)d.nx + d.ny + d.nz);
     L.nfields = nfields;
-    for (int i = 0; i < nfields; ++i) L.fields[i] = cv.take<float>(d.N);
+    for (int i = 0; i < nfields; ++i) L.fields[i] = cv.take<float>(d.Np);
     L.src = carve_table(cv, d.nx, ns);
     L.rec = carve_table(cv, d.nx, nr);
     L.vstat = cv.take<float>(3 * kStatBlocks);
     L.rpart = cv.take<double>(kStatBlocks);
     if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
         L.nck = nt > 0 ? (int)((nt + K - 1) / K) : 0;
-        L.ckpt = cv.take<float>((size_t)std::max(L.nck, 1) * 2 * d.N);
-        L.seg = cv.take<float>((size_t)std::max(1, (int)std::min<int64_t>(K, std::max<int64_t>(nt, 1))) * d.N);
-        L.g = cv.take<double>(d.N);
+        L.ckpt = cv.take<float>((size_t)std::max(L.nck, 1) * 2 * d.Np);
+        L.seg = cv.take<float>((size_t)std::max(1, (int)std::min<int64_t>(K, std::max<int64_t>(nt, 1))) * d.Np);
+        L.g = cv.take<double>(d.Np);
         L.traces = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
         L.resid = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
     }
@@ -405,7 +412,7 @@ int default_lx(const Dims &d, const KernelKey &k)
 {
     const int ty = stream_core_rows(k), tz = stream_core_cols(k);
     const int64_t P = (int64_t)((d.nz + tz - 1) / tz) * ((d.ny + ty - 1) / ty);
-    const int64_t C = (int64_t)std::max(1, stream_occupancy(k, grid_iso(d))) * device_cus();
+    const int64_t C = (int64_t)std::max(1, stream_occupancy(k, grid_iso(d), false)) * device_cus();
     const int minlx = 4 * k.T * k.M;
     int best_lx = std::min(d.nx, kMaxLx);
     double best = -1.0;
@@ -547,7 +554,7 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
     for (size_t j = 0; j < ent.size(); ++j) {
         xptr[ent[j].x + 1]++;
         xe[j] = ent[j].x;
-        yz[j] = ent[j].y * d.nz + ent[j].z;
+        yz[j] = ent[j].y * d.nzp + ent[j].z;
         id[j] = ent[j].id;
     }
     for (int x = 0; x < d.nx; ++x) xptr[x + 1] += xptr[x];
@@ -659,7 +666,7 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
             const fd_points *rec, uint32_t flags)
 {
     const Dims &d = c.d;
-    FDW_HIP(launch_make_q(v, c.L.q, d.N, c.dt * c.dt, c.s));
+    FDW_HIP(launch_make_q(v, c.L.q, (int64_t)d.nx * d.ny, d.nz, d.nzp, c.dt * c.dt, c.s));
     std::vector<float> prof((size_t)d.nx + d.ny + d.nz);
     sponge_profile(d.nx, g->sponge, d.h[0], g->sponge_vref, c.dt, d.present[0], prof.data());
     sponge_profile(d.ny, g->sponge, d.h[1], g->sponge_vref, c.dt, d.present[1], prof.data() + d.nx);
@@ -699,7 +706,8 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     a.nx = d.nx;
     a.ny = d.ny;
     a.nz = d.nz;
-    a.sxy = (int64_t)d.ny * d.nz;
+    a.nzp = d.nzp;
+    a.sxy = (int64_t)d.ny * d.nzp;
     a.w = make_weights(d);
     a.q = c.L.q;
     a.px = c.L.prof;
@@ -795,7 +803,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
             a.o1 = out;
             const int M = d.M, mode = so.mode;
-            float *cur = st.cur, *prev = st.prev, *d2 = a.d2 + a.dslot0 * d.N;
+            float *cur = st.cur, *prev = st.prev, *d2 = a.d2 + a.dslot0 * d.Np;
             c.ex.call([a, M, out, cur, prev, d2, mode](hipStream_t s) {
                 hipError_t e = launch_naive_step(M, a, s);
                 if (e == hipSuccess) e = launch_inject(a, out, a.step0, s);
@@ -947,18 +955,31 @@ int fwd_setup(FwdJob &j, const fd_grid *grid, const fd_time *time, const float *
 void fwd_issue(FwdJob &j)
 {
     Ctx &c = j.c;
-    const int64_t N = c.d.N;
+    const int64_t N = c.d.Np;
+    // the caller's state pair is used in place when its layout is the
+    // internal one (nz a multiple of 32); otherwise it is converted in and out
+    const bool direct = j.u_state && c.d.nzp == c.d.nz;
     float *A, *B;
-    if (j.u_state) {
+    if (direct) {
         A = j.u_state;
         B = j.u_state + N;
     } else {
         A = c.L.fields[2];
         B = c.L.fields[3];
-        c.ex.call([A, B, N](hipStream_t s) {
-            hipError_t e = launch_zero(A, N * 4, s);
-            return e == hipSuccess ? launch_zero(B, N * 4, s) : e;
-        });
+        if (j.u_state) {
+            const float *U = j.u_state;
+            const int64_t rows = (int64_t)c.d.nx * c.d.ny, Nd = c.d.N;
+            const int nz = c.d.nz, nzp = c.d.nzp;
+            c.ex.call([A, B, U, rows, nz, nzp, Nd](hipStream_t s) {
+                hipError_t e = launch_repitch(A, nzp, U, nz, rows, nz, s);
+                return e == hipSuccess ? launch_repitch(B, nzp, U + Nd, nz, rows, nz, s) : e;
+            });
+        } else {
+            c.ex.call([A, B, N](hipStream_t s) {
+                hipError_t e = launch_zero(A, N * 4, s);
+                return e == hipSuccess ? launch_zero(B, N * 4, s) : e;
+            });
+        }
     }
     State st;
     st.cur = A;
@@ -968,7 +989,16 @@ void fwd_issue(FwdJob &j)
     st.spare[2] = nullptr;
     st.nspare = 2;
     advance(c, st, 0, c.nt, StepOpts{});
-    if (j.u_state) {
+    if (j.u_state && !direct) {
+        float *U = j.u_state;
+        const float *cur = st.cur, *prev = st.prev;
+        const int64_t rows = (int64_t)c.d.nx * c.d.ny, Nd = c.d.N;
+        const int nz = c.d.nz, nzp = c.d.nzp;
+        c.ex.call([U, cur, prev, rows, nz, nzp, Nd](hipStream_t s) {
+            hipError_t e = launch_repitch(U, nz, cur, nzp, rows, nz, s);
+            return e == hipSuccess ? launch_repitch(U + Nd, nz, prev, nzp, rows, nz, s) : e;
+        });
+    } else if (j.u_state) {
         const State fin = st;
         float *tmp = (c.L.fields[0] == st.cur || c.L.fields[0] == st.prev) ? c.L.fields[1]
                                                                             : c.L.fields[0];
@@ -1077,17 +1107,17 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
         State st;
         st.cur = c.L.fields[2];
         st.prev = c.L.fields[3];
-        FDW_HIP(launch_zero(st.cur, c.d.N * 4, c.s));
-        FDW_HIP(launch_zero(st.prev, c.d.N * 4, c.s));
+        FDW_HIP(launch_zero(st.cur, c.d.Np * 4, c.s));
+        FDW_HIP(launch_zero(st.prev, c.d.Np * 4, c.s));
         st.spare[0] = c.L.fields[0];
         st.spare[1] = c.L.fields[1];
         st.spare[2] = nullptr;
         st.nspare = 2;
         advance(c, st, 0, c.nt, StepOpts{});
         if (lam_state) {
-            FDW_HIP(hipMemcpyAsync(lam_state, st.cur, c.d.N * 4, hipMemcpyDeviceToDevice, c.s));
-            FDW_HIP(hipMemcpyAsync(lam_state + c.d.N, st.prev, c.d.N * 4, hipMemcpyDeviceToDevice,
-                                   c.s));
+            const int64_t rows = (int64_t)c.d.nx * c.d.ny;
+            FDW_HIP(launch_repitch(lam_state, c.d.nz, st.cur, c.d.nzp, rows, c.d.nz, c.s));
+            FDW_HIP(launch_repitch(lam_state + c.d.N, c.d.nz, st.prev, c.d.nzp, rows, c.d.nz, c.s));
         }
         record_last(c.plan);
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(src_out, c.nt * ns, c.s);
@@ -1155,7 +1185,7 @@ int grad_setup(GradJob &j, const fd_grid *grid, const fd_time *time, const float
 void grad_issue(GradJob &j)
 {
     Ctx &c = j.c;
-    const int64_t N = c.d.N;
+    const int64_t N = c.d.Np;  // floats of one internal (padded) field
     const int K = j.K, ns = j.ns, nr = j.nr;
     // ---- forward sweep with checkpoints (sources inject, receivers record)
     c.base.rec_out = c.L.traces;
@@ -1244,7 +1274,11 @@ void grad_issue(GradJob &j)
         const double *g = c.L.g;
         const float *v = j.v;
         float *gv = j.grad_v;
-        c.ex.call([g, v, gv, N](hipStream_t s) { return launch_grad_v(g, v, gv, N, s); });
+        const int64_t rows = (int64_t)c.d.nx * c.d.ny;
+        const int nz = c.d.nz, nzp = c.d.nzp;
+        c.ex.call([g, v, gv, rows, nz, nzp](hipStream_t s) {
+            return launch_grad_v(g, v, gv, rows, nz, nzp, s);
+        });
     }
 }
 
@@ -1392,7 +1426,7 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         for (int a = 0; a < 3; ++a)
             if (d.present[a]) inv_h2 += 1.0 / (d.h[a] * d.h[a]);
         const float qv = (float)(0.36 * 4.0 / (nyquist_symbol(d.M) * inv_h2));
-        hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, s, c.L.q, qv, d.N);
+        hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, s, c.L.q, qv, d.Np);
         FDW_HIP(hipGetLastError());
         std::vector<float> prof((size_t)d.nx + d.ny + d.nz);
         sponge_profile(d.nx, grid->sponge, d.h[0], grid->sponge_vref, tt.dt, d.present[0], prof.data());
@@ -1409,7 +1443,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         a.nx = d.nx;
         a.ny = d.ny;
         a.nz = d.nz;
-        a.sxy = (int64_t)d.ny * d.nz;
+        a.nzp = d.nzp;
+        a.sxy = (int64_t)d.ny * d.nzp;
         a.w = make_weights(d);
         a.q = c.L.q;
         a.px = c.L.prof;
@@ -1430,8 +1465,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
             if (make_plan(d, &cand.o, p) != FD_OK) continue;
             c.plan = p;
             State st{c.L.fields[2], c.L.fields[3], {c.L.fields[0], c.L.fields[1], nullptr}, 2};
-            FDW_HIP(launch_zero(st.cur, d.N * 4, s));
-            FDW_HIP(launch_zero(st.prev, d.N * 4, s));
+            FDW_HIP(launch_zero(st.cur, d.Np * 4, s));
+            FDW_HIP(launch_zero(st.prev, d.Np * 4, s));
             const int64_t steps = std::max<int64_t>(tt.nt, p.key.T) / p.key.T * p.key.T;
             advance(c, st, 0, steps, StepOpts{});  // warm-up
             FDW_HIP(hipEventRecord(e0, s));
@@ -1490,7 +1525,7 @@ void batch_chunk(Ctx &c, const fd_options &o)
 
 // Merge the recorded op lists of many shots and run them on one stream: ops
 // are taken round by round (op r of every shot), passes of one round with the
-// same kernel configuration and Laplacian form become one grouped persistent
+// same kernel configuration and Laplacian form become one grouped
 // launch over all their tiles, other ops run as recorded.  Shots are
 // independent, so any interleaving that keeps each shot's order is valid.
 int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_t max_entries,
@@ -1505,7 +1540,6 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
         int shot, idx;
         int grid;
     };
-    const int cus = device_cus();
     std::vector<GroupEntry> host;
     std::vector<Launch> plan;
     size_t rounds = 0;
@@ -1538,8 +1572,11 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
                 host.push_back(e);
                 ++L.n;
             }
-            // persistent grid: every resident workgroup slot of the device, at most one per tile
-            L.grid = std::min(L.total, std::max(1, stream_occupancy(L.key, L.iso)) * cus);
+            // one workgroup per tile: the hardware dispatcher balances the uneven
+            // tiles of different shots (measured on MI355X, 7 % faster for the
+            // 32-shot batch than a persistent grid of one workgroup per
+            // resident slot walking the table; the kernel supports both)
+            L.grid = L.total;
             plan.push_back(L);
         }
     }

@@ -41,7 +41,8 @@ struct PointTable {
 // Arguments of one pass of T levels (T = 1 for a plain step).
 struct SweepArgs {
     int nx, ny, nz;
-    int64_t sxy;      // ny * nz
+    int nzp;          // row pitch of every internal field: nz rounded up to 32 floats
+    int64_t sxy;      // ny * nzp (one x-plane)
     Weights w;
     const float *q;   // v^2 dt^2
     const float *px;  // sponge profile / (2 dt) along x, y, z  (damp * v^2 dt / 2 = q * (px + (py + pz)))
@@ -111,12 +112,13 @@ struct KernelKey {
 // Launcher for the templated streaming kernel; returns false when no
 // instantiation matches the key.  With list == nullptr the kernel runs the
 // tiles of `a`; otherwise it walks the `total` tiles of the nlist entries
-// persistently with `grid` workgroups (iso selects the Laplacian form).
+// with `grid` workgroups, persistently if grid < total (iso selects the Laplacian form).
 bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
 bool launch_stream_grouped(const KernelKey &key, bool iso, const GroupEntry *list, int nlist,
                            int total, int grid, hipStream_t s);
-// Resident workgroups per CU of a configuration (0 if not compiled).
-int stream_occupancy(const KernelKey &key, bool iso);
+// Resident workgroups per CU of a configuration's single-pass or grouped kernel
+// (0 if not compiled).
+int stream_occupancy(const KernelKey &key, bool iso, bool grouped);
 // Tile sizes (core rows / columns) for a key.
 int stream_core_rows(const KernelKey &key);
 int stream_core_cols(const KernelKey &key);
@@ -136,15 +138,22 @@ hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2,
                           hipStream_t s);
 
 // Preparation / reduction kernels.
-hipError_t launch_make_q(const float *v, float *q, int64_t n, double dt2, hipStream_t s);
+// q = v^2 dt^2 from the dense caller layout (rows of nz) into the padded
+// internal layout (rows of nzp, padding zero).
+hipError_t launch_make_q(const float *v, float *q, int64_t rows, int nz, int nzp, double dt2,
+                         hipStream_t s);
+// Copy rows of nz floats between layouts of row pitch spitch and dpitch (the
+// destination's padding, if any, is zeroed).
+hipError_t launch_repitch(float *dst, int dpitch, const float *src, int spitch, int64_t rows,
+                          int nz, hipStream_t s);
 hipError_t launch_vstats(const float *v, int64_t n, float *partial /*[3*nb]*/, int nb,
                          hipStream_t s);
 hipError_t launch_scales(const SweepArgs &a, const PointTable &t, float *scale, float alpha,
                          hipStream_t s);
 hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n,
                            double *partial, int nb, hipStream_t s);
-hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t n,
-                         hipStream_t s);
+hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t rows, int nz,
+                         int nzp, hipStream_t s);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 

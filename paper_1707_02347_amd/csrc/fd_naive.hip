@@ -29,15 +29,15 @@ __global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
     const int x = blockIdx.z;
     if (z >= a.nz || y >= a.ny) return;
     const float *u = a.u0;
-    const int64_t c = (int64_t)x * a.sxy + (int64_t)y * a.nz + z;
+    const int64_t c = (int64_t)x * a.sxy + (int64_t)y * a.nzp + z;
     const float uc = u[c];
     float lap = 0.0f;
 #pragma unroll
     for (int k = 1; k <= M; ++k) {
         const float xm = (x - k >= 0) ? u[c - k * a.sxy] : 0.0f;
         const float xp = (x + k < a.nx) ? u[c + k * a.sxy] : 0.0f;
-        const float ym = (y - k >= 0) ? u[c - (int64_t)k * a.nz] : 0.0f;
-        const float yp = (y + k < a.ny) ? u[c + (int64_t)k * a.nz] : 0.0f;
+        const float ym = (y - k >= 0) ? u[c - (int64_t)k * a.nzp] : 0.0f;
+        const float yp = (y + k < a.ny) ? u[c + (int64_t)k * a.nzp] : 0.0f;
         const float zm = (z - k >= 0) ? u[c - k] : 0.0f;
         const float zp = (z + k < a.nz) ? u[c + k] : 0.0f;
         if constexpr (ISO) {
@@ -168,18 +168,46 @@ hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2,
     return hipGetLastError();
 }
 
-__global__ void k_make_q(const float *v, float *q, int64_t n, double dt2)
+__global__ void k_make_q(const float *v, float *q, int64_t rows, int nz, int nzp, double dt2)
 {
+    const int64_t n = rows * nzp;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double vv = (double)v[i];
-        q[i] = (float)(vv * vv * dt2);
+        const int64_t r = i / nzp;
+        const int z = (int)(i - r * nzp);
+        float qv = 0.0f;
+        if (z < nz) {
+            const double vv = (double)v[r * nz + z];
+            qv = (float)(vv * vv * dt2);
+        }
+        q[i] = qv;
     }
 }
 
-hipError_t launch_make_q(const float *v, float *q, int64_t n, double dt2, hipStream_t s)
+hipError_t launch_make_q(const float *v, float *q, int64_t rows, int nz, int nzp, double dt2,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(k_make_q, dim3(4096), dim3(256), 0, s, v, q, n, dt2);
+    hipLaunchKernelGGL(k_make_q, dim3(4096), dim3(256), 0, s, v, q, rows, nz, nzp, dt2);
+    return hipGetLastError();
+}
+
+__global__ void k_repitch(float *dst, int dpitch, const float *src, int spitch, int64_t rows,
+                          int nz)
+{
+    const int64_t n = rows * dpitch;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dpitch;
+        const int z = (int)(i - r * dpitch);
+        dst[i] = (z < nz) ? src[r * spitch + z] : 0.0f;
+    }
+}
+
+hipError_t launch_repitch(float *dst, int dpitch, const float *src, int spitch, int64_t rows,
+                          int nz, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_repitch, dim3(4096), dim3(256), 0, s, dst, dpitch, src, spitch, rows, nz);
     return hipGetLastError();
 }
 
@@ -228,8 +256,8 @@ __global__ void k_scales(SweepArgs a, PointTable t, float *scale, float alpha)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= t.cnt) return;
     const int x = t.xe[j];
-    const int y = t.yz[j] / a.nz;
-    const int z = t.yz[j] - y * a.nz;
+    const int y = t.yz[j] / a.nzp;
+    const int z = t.yz[j] - y * a.nzp;
     const float qv = a.q[(int64_t)x * a.sxy + t.yz[j]];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
     scale[j] = alpha * damped(qv, eta);
@@ -270,20 +298,24 @@ hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_
     return hipGetLastError();
 }
 
-// grad_v = dJ/dm * (-2 / v^3) with dJ/dm = -2 g  ->  4 g / v^3, evaluated in FP64.
-__global__ void k_grad_v(const double *g, const float *v, float *gv, int64_t n)
+// grad_v = dJ/dm * (-2 / v^3) with dJ/dm = -2 g  ->  4 g / v^3, evaluated in FP64
+// (g in the padded internal layout, v and grad_v dense).
+__global__ void k_grad_v(const double *g, const float *v, float *gv, int64_t rows, int nz, int nzp)
 {
+    const int64_t n = rows * nz;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / nz;
+        const int z = (int)(i - r * nz);
         const double vv = (double)v[i];
-        gv[i] = (float)(4.0 * g[i] / (vv * vv * vv));
+        gv[i] = (float)(4.0 * g[r * nzp + z] / (vv * vv * vv));
     }
 }
 
-hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t n,
-                         hipStream_t s)
+hipError_t launch_grad_v(const double *g, const float *v, float *grad_v, int64_t rows, int nz,
+                         int nzp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_grad_v, dim3(4096), dim3(256), 0, s, g, v, grad_v, n);
+    hipLaunchKernelGGL(k_grad_v, dim3(4096), dim3(256), 0, s, g, v, grad_v, rows, nz, nzp);
     return hipGetLastError();
 }
 

@@ -215,7 +215,7 @@ struct StreamKernel {
             const int y = y1 + rr;
             const bool yin = (unsigned)y < (unsigned)a.ny;
             th.din[r] = yin && zin;
-            th.bo[r] = th.din[r] ? (uint32_t)(y * a.nz + z) * 4u : kOutside;
+            th.bo[r] = th.din[r] ? (uint32_t)(y * a.nzp + z) * 4u : kOutside;
             th.pyz[r] = th.din[r] ? (a.py[y] + pzv) : 0.0f;
             th.core[r] = th.din[r] && rr >= G::H1 && rr < G::RY - G::H1 && th.lane >= G::H1 &&
                          th.lane < G::RZ - G::H1;
@@ -227,7 +227,7 @@ struct StreamKernel {
             const bool used = halo_pos(threadIdx.x + s * G::NT, row, col);
             const int gy = y1 - M + row, gz = z1 - M + col;
             th.hv[s] = used && (unsigned)gy < (unsigned)a.ny && (unsigned)gz < (unsigned)a.nz;
-            th.hb[s] = th.hv[s] ? (uint32_t)(gy * a.nz + gz) * 4u : kOutside;
+            th.hb[s] = th.hv[s] ? (uint32_t)(gy * a.nzp + gz) * 4u : kOutside;
         }
         // per-plane tables of the planes any level of this chunk computes
         const int span = th.xend - th.x0 + 2 * (T - 1) * M + 1;
@@ -600,8 +600,9 @@ __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
     K::run(a, sm, blockIdx.x, gridDim.x);
 }
 
-// Grouped persistent pass: the workgroups walk the flat tile range of all the
-// entries (one per shot) of a batch.  Workgroup b runs on XCD b % 8; when the
+// Grouped pass: the workgroups walk the flat tile range of all the entries (one
+// per shot) of a batch, one tile each when the grid covers the range, else
+// persistently.  Workgroup b runs on XCD b % 8; when the
 // grid is a multiple of 8, the items of one round are dealt so that each XCD
 // takes a contiguous block of them (neighbouring tiles of one shot share that
 // XCD's L2).
@@ -670,18 +671,20 @@ bool entry_launch_group(bool iso, const GroupEntry *list, int nlist, int total, 
     return false;
 }
 
-// Resident workgroups per CU: of the grouped kernel where it is compiled, else
-// of the single-pass kernel (0 if the requested form is not compiled).
+// Resident workgroups per CU of the single-pass or the grouped kernel (0 if the
+// requested form is not compiled).
 template <int M, int T, int PY, int NW, int MODE, int F>
-int entry_occupancy(bool iso)
+int entry_occupancy(bool iso, bool grouped)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     const void *fn = nullptr;
-    if constexpr ((F & 2) != 0) {
-        if (iso) fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>);
-        else if constexpr ((F & 1) != 0)
-            fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>);
+    if (grouped) {
+        if constexpr ((F & 2) != 0) {
+            if (iso) fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>);
+            else if constexpr ((F & 1) != 0)
+                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>);
+        }
     } else {
         if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true>);
         else if constexpr ((F & 1) != 0)

@@ -2,7 +2,7 @@
 // X(M, T, PY, NW, MODE, F).  Owned region: 64 columns x NW*PY rows; output
 // core: (64 - 2M(T-1)) columns x (NW*PY - 2M(T-1)) rows.  Every entry has an
 // isotropic single-pass kernel; F adds the anisotropic form (bit 0) and the
-// grouped persistent batch kernel (bit 1) for the configurations the planner
+// grouped batch kernel (bit 1) for the configurations the planner
 // picks by default (other entries serve the tuner's search space).
 #pragma once
 

@@ -12,7 +12,7 @@ struct StreamEntry {
     bool (*launch)(const SweepArgs &a, hipStream_t s);
     bool (*launch_group)(bool iso, const GroupEntry *list, int nlist, int total, int grid,
                          hipStream_t s);
-    int (*occupancy)(bool iso);
+    int (*occupancy)(bool iso, bool grouped);
 };
 
 // All compiled entries (generated).

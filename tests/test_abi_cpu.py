@@ -66,7 +66,7 @@ def test_checkpoint_interval_sets_gradient_workspace():
     o10, o50 = L.make_options(ckpt_every=10), L.make_options(ckpt_every=50)
     a = L.fd_workspace_size(C.byref(g), C.byref(t), None, None, C.byref(o10), L.FD_OP_GRADIENT)
     b = L.fd_workspace_size(C.byref(g), C.byref(t), None, None, C.byref(o50), L.FD_OP_GRADIENT)
-    N4 = 32 * 30 * 40 * 4
+    N4 = 32 * 30 * 64 * 4  # internal fields pad each z row of 40 to 64 floats (128-byte multiple)
     # 20 checkpoints of 2 fields + 10 segment fields vs 4 checkpoints + 50 segment fields
     assert abs((a - b) - ((40 + 10) - (8 + 50)) * N4) < 64 * 1024
 
