@@ -1,0 +1,63 @@
+"""The autotuner (fd_autotune): it returns a compiled configuration, keeps the
+fields the caller fixed, the configuration it picks reproduces the untiled
+sweep bit for bit, automatic plans use it afterwards, and a cache file records
+it."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_1707_02347_amd import _lib as L
+from paper_1707_02347_amd import api
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def case(shape=(48, 40, 72), so=8, nt=24):
+    v = synth.smooth_velocity(shape, seed=11, sigma=4.0)
+    dt = 0.8 * 0.45 * 10.0 / float(v.max())
+    src = synth.centre_source(shape, depth=8)
+    rec = synth.receiver_line(shape, 12, depth=8)
+    amp = torch.from_numpy(synth.ricker(nt, dt, 25.0)[:, None].copy()).to(DEV)
+    return v.to(DEV), [10.0] * 3, so, nt, dt, src, rec, amp
+
+
+def run(v, h, so, nt, dt, src, rec, amp, **opts):
+    return api.forward(v, h, so, nt, dt, src, amp, rec, sponge=6, vref=4500.0, **opts)
+
+
+def test_tuned_configuration_is_exact_and_used_by_automatic_plans(tmp_path, monkeypatch):
+    v, h, so, nt, dt, src, rec, amp = case()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FD_AUTOTUNE_CACHE", str(cache))
+    tuned = api.autotune(tuple(v.shape), h, so, dt, sponge=6, vref=4500.0)
+    print("tuned:", tuned)
+    assert tuned["variant"] in (L.FD_VARIANT_NAIVE, L.FD_VARIANT_STREAM, L.FD_VARIANT_TBLOCK)
+    assert tuned["tblock"] >= 1
+    base = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
+    out = run(v, h, so, nt, dt, src, rec, amp, **tuned)
+    assert torch.equal(out["rec"], base["rec"])
+    # an automatic plan for the same grid now takes the tuned configuration
+    auto = run(v, h, so, nt, dt, src, rec, amp)
+    cfg = api.last_config()
+    assert cfg["variant"] == tuned["variant"] and cfg["tblock"] == tuned["tblock"]
+    if tuned["variant"] != L.FD_VARIANT_NAIVE:
+        assert tuple(cfg["tile"]) == tuple(tuned["tile"])
+    assert torch.equal(auto["rec"], base["rec"])
+    # the choice is appended to the cache file, keyed by (ndim, n, so, arch)
+    line = cache.read_text().strip().splitlines()[-1].split()
+    assert [int(x) for x in line[:5]] == [3, *v.shape, so] and line[5] == "gfx950"
+    assert int(line[6]) == tuned["variant"]
+
+
+def test_tuner_keeps_fixed_fields():
+    v, h, so, nt, dt, src, rec, amp = case((40, 36, 70), so=4)
+    tuned = api.autotune(tuple(v.shape), h, so, dt, sponge=6, vref=4500.0, variant=L.FD_VARIANT_TBLOCK,
+                         tblock=2)
+    assert tuned["variant"] == L.FD_VARIANT_TBLOCK and tuned["tblock"] == 2
+    base = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
+    out = run(v, h, so, nt, dt, src, rec, amp, **tuned)
+    assert torch.equal(out["rec"], base["rec"])
