@@ -263,7 +263,7 @@ struct Carver {
 constexpr int kStatBlocks = 256;
 
 struct TableBufs {
-    int32_t *xptr, *xe, *yz, *id;
+    int32_t *xptr, *xe, *yz, *id, *box;
     float *scale;
 };
 
@@ -293,6 +293,7 @@ TableBufs carve_table(Carver &cv, int nx, int cnt)
     t.yz = cv.take<int32_t>(std::max(cnt, 1));
     t.id = cv.take<int32_t>(std::max(cnt, 1));
     t.scale = cv.take<float>(std::max(cnt, 1));
+    t.box = cv.take<int32_t>((size_t)nx * 4);
     return t;
 }
 
@@ -551,11 +552,31 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
                   hipStream_t s)
 {
     std::vector<int32_t> xptr(d.nx + 1, 0), xe(ent.size()), yz(ent.size()), id(ent.size());
+    // per-plane bounding box of the entries, so that a tile skips the planes
+    // whose points it cannot hold without reading their entries
+    std::vector<int32_t> box((size_t)d.nx * 4);
+    for (int x = 0; x < d.nx; ++x) {
+        box[4 * x + 0] = box[4 * x + 2] = 1;
+        box[4 * x + 1] = box[4 * x + 3] = 0;
+    }
+    std::vector<bool> seen(d.nx, false);
     for (size_t j = 0; j < ent.size(); ++j) {
-        xptr[ent[j].x + 1]++;
-        xe[j] = ent[j].x;
-        yz[j] = ent[j].y * d.nzp + ent[j].z;
-        id[j] = ent[j].id;
+        const Entry &e = ent[j];
+        xptr[e.x + 1]++;
+        xe[j] = e.x;
+        yz[j] = e.y * d.nzp + e.z;
+        id[j] = e.id;
+        int32_t *bx = &box[4 * (size_t)e.x];
+        if (!seen[e.x]) {
+            bx[0] = bx[1] = e.y;
+            bx[2] = bx[3] = e.z;
+            seen[e.x] = true;
+        } else {
+            bx[0] = std::min(bx[0], e.y);
+            bx[1] = std::max(bx[1], e.y);
+            bx[2] = std::min(bx[2], e.z);
+            bx[3] = std::max(bx[3], e.z);
+        }
     }
     for (int x = 0; x < d.nx; ++x) xptr[x + 1] += xptr[x];
     FDW_HIP(hipMemcpyAsync(b.xptr, xptr.data(), xptr.size() * 4, hipMemcpyHostToDevice, s));
@@ -563,6 +584,7 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
         FDW_HIP(hipMemcpyAsync(b.xe, xe.data(), xe.size() * 4, hipMemcpyHostToDevice, s));
         FDW_HIP(hipMemcpyAsync(b.yz, yz.data(), yz.size() * 4, hipMemcpyHostToDevice, s));
         FDW_HIP(hipMemcpyAsync(b.id, id.data(), id.size() * 4, hipMemcpyHostToDevice, s));
+        FDW_HIP(hipMemcpyAsync(b.box, box.data(), box.size() * 4, hipMemcpyHostToDevice, s));
     }
     FDW_HIP(hipStreamSynchronize(s));
 }
@@ -575,6 +597,7 @@ PointTable as_table(const TableBufs &b, int stride, int cnt, bool with_scale)
     t.yz = b.yz;
     t.id = b.id;
     t.scale = with_scale ? b.scale : nullptr;
+    t.box = b.box;
     t.stride = stride;
     t.cnt = cnt;
     return t;

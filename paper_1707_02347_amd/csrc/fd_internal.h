@@ -34,6 +34,8 @@ struct PointTable {
     const int32_t *yz;    // [cnt] y * nz + z
     const int32_t *id;    // [cnt] original point index (column of amp / record arrays)
     const float *scale;   // [cnt] injection scale (sources only), else nullptr
+    const int32_t *box;   // [nx][4] bounding box of each plane's entries: min y, max y,
+                          // min z, max z (empty plane: min > max)
     int32_t stride;       // number of original points (row length of amp / record)
     int32_t cnt;          // number of entries
 };

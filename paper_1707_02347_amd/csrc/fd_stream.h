@@ -142,8 +142,8 @@ struct StreamKernel {
         float s0[2][G::L0H * G::L0W];
         float s1[(T > 1) ? (T - 1) : 1][2][(T > 1) ? (G::RY + 2 * M) * G::RZ : 1];
         float px[G::SPAN];
-        int ixp[G::SPAN];
-        int rxp[G::SPAN];
+        int ixb[G::SPAN], ixe[G::SPAN];  // per plane: source entries this tile may hold
+        int rxb[G::SPAN], rxe[G::SPAN];  // per plane: receiver entries its core may hold
     };
 
     static constexpr bool IMG = (MODE == kImaging);
@@ -229,14 +229,34 @@ struct StreamKernel {
             th.hv[s] = used && (unsigned)gy < (unsigned)a.ny && (unsigned)gz < (unsigned)a.nz;
             th.hb[s] = th.hv[s] ? (uint32_t)(gy * a.nzp + gz) * 4u : kOutside;
         }
-        // per-plane tables of the planes any level of this chunk computes
-        const int span = th.xend - th.x0 + 2 * (T - 1) * M + 1;
+        // per-plane tables of the planes any level of this chunk computes: the
+        // sponge profile and each plane's range of point entries, emptied when
+        // the bounding box of the plane's points misses this tile (its owned
+        // region for sources, its output core for receivers)
+        const int span = th.xend - th.x0 + 2 * (T - 1) * M;
         for (int j = threadIdx.x; j < span; j += G::NT) {
             const int c = th.cbase + j;
             const bool cin = (unsigned)c < (unsigned)a.nx;
             sm.px[j] = cin ? a.px[c] : 0.0f;
-            sm.ixp[j] = (a.inj.cnt > 0 && c >= 0 && c <= a.nx) ? a.inj.xptr[c] : 0;
-            sm.rxp[j] = (a.rec.cnt > 0 && c >= 0 && c <= a.nx) ? a.rec.xptr[c] : 0;
+            sm.ixb[j] = sm.ixe[j] = 0;
+            if (cin && a.inj.cnt > 0) {
+                const int b = a.inj.xptr[c], e = a.inj.xptr[c + 1];
+                const int32_t *bx = a.inj.box + 4 * c;
+                if (b < e && bx[1] >= y1 && bx[0] < y1 + G::RY && bx[3] >= z1 && bx[2] < z1 + G::RZ) {
+                    sm.ixb[j] = b;
+                    sm.ixe[j] = e;
+                }
+            }
+            sm.rxb[j] = sm.rxe[j] = 0;
+            if (cin && a.rec.cnt > 0) {
+                const int b = a.rec.xptr[c], e = a.rec.xptr[c + 1];
+                const int32_t *bx = a.rec.box + 4 * c;
+                if (b < e && bx[1] >= y1 + G::H1 && bx[0] < y1 + G::H1 + G::TY &&
+                    bx[3] >= z1 + G::H1 && bx[2] < z1 + G::H1 + G::TZ) {
+                    sm.rxb[j] = b;
+                    sm.rxe[j] = e;
+                }
+            }
         }
         // (the first barrier of the loop orders these writes before any read)
 
@@ -505,8 +525,8 @@ struct StreamKernel {
             }
             const int step = a.step0 + t - 1;
             {
-                const int jb = __builtin_amdgcn_readfirstlane(sm.ixp[tj]);
-                const int je = __builtin_amdgcn_readfirstlane(sm.ixp[tj + 1]);
+                const int jb = __builtin_amdgcn_readfirstlane(sm.ixb[tj]);
+                const int je = __builtin_amdgcn_readfirstlane(sm.ixe[tj]);
                 if (jb < je) {
                     const float *arow = a.amp + (a.abase + (int64_t)a.adir * step) * a.inj.stride;
                     for (int j = jb; j < je; ++j) {
@@ -523,8 +543,8 @@ struct StreamKernel {
                 }
             }
             if (c >= th.x0 && c < th.xend) {
-                const int jb = __builtin_amdgcn_readfirstlane(sm.rxp[tj]);
-                const int je = __builtin_amdgcn_readfirstlane(sm.rxp[tj + 1]);
+                const int jb = __builtin_amdgcn_readfirstlane(sm.rxb[tj]);
+                const int je = __builtin_amdgcn_readfirstlane(sm.rxe[tj]);
                 if (jb < je) {
                     float *orow = a.rec_out + (a.rbase + (int64_t)a.rdir * step) * a.rec.stride;
                     for (int j = jb; j < je; ++j) {
