@@ -178,6 +178,87 @@ def test_full_size_cfg2_tiled_equals_untiled():
     assert float(outs[0]["u"].abs().max()) > 0
 
 
+def test_full_size_cfg3_tiled_and_time_blocked_equal_untiled():
+    """512^3, so 16, 1000 steps, 40-cell sponge: the benchmark's space-tiled and
+    time-blocked launch configurations reproduce the untiled sweep bit for bit."""
+    import bench
+
+    cs = bench.workload("cfg3", device=DEV)
+    outs = []
+    for opt in (dict(variant=L.FD_VARIANT_NAIVE), bench.launch_options("cfg3"), bench.launch_options("cfg3_t2")):
+        out = api.forward(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], None,
+                          sponge=cs["sponge"], vref=cs["vref"], **opt)
+        outs.append(out["u"])
+        del out
+    assert float(outs[0].abs().max()) > 0
+    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("so", [2, 4, 8])
+def test_full_size_time_blocking_study_configs_equal_untiled(so):
+    """512^3 with the space orders and the time-blocked configurations the
+    benchmark's time-blocking study times (48 steps)."""
+    import bench
+
+    cs = bench.workload("cfg3", device=DEV)
+    nt = 48
+    dt = 0.8 * bench.courant_max(so, 3) * 10.0 / 4500.0
+    amp = torch.from_numpy(synth.ricker(nt, dt, 15.0)[:, None].copy()).to(DEV)
+    outs = []
+    for opt in (dict(variant=L.FD_VARIANT_NAIVE), *bench.TIME_BLOCKING[so]):
+        out = api.forward(cs["v"], cs["h"], so, nt, dt, cs["src"], amp, None, sponge=cs["sponge"],
+                          vref=cs["vref"], **opt)
+        outs.append(out["u"])
+        del out
+    assert float(outs[0].abs().max()) > 0
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
+
+
+def test_full_size_cfg3_sampled_points_match_oracle():
+    """512^3 so 16 at the benchmark's launch configuration: a Gaussian initial
+    state advanced 6 steps, single points checked against the oracle on their
+    cube of dependence (radius 6 M)."""
+    import bench
+
+    cs = bench.workload("cfg3", device=DEV)
+    nt, so, M = 6, cs["so"], cs["so"] // 2
+    shape = tuple(cs["v"].shape)
+    g = torch.from_numpy(synth.gaussian_field(shape, 0.3)).to(DEV)
+    out = api.forward(cs["v"], cs["h"], so, nt, cs["dt"], None, None, None, u0=g, um1=g,
+                      **bench.launch_options("cfg3"))
+    u = out["u"].cpu().numpy()
+    R = nt * M
+    v = cs["v"].cpu().numpy()
+    gh = g.cpu().numpy()
+    for p in [(256, 256, 256), (0, 511, 0), (511, 3, 300), (100, 400, 511)]:
+        sl = tuple(slice(max(0, c - R), min(n, c + R + 1)) for c, n in zip(p, shape))
+        loc = tuple(c - s.start for c, s in zip(p, sl))
+        prob = oracle.Problem(v[sl].astype(np.float64), cs["h"], so, nt, cs["dt"])
+        ref = oracle.forward(prob, u0=gh[sl].astype(np.float64), um1=gh[sl].astype(np.float64))["u"]
+        assert abs(u[p] - ref[loc]) <= 1e-5 * max(abs(ref[loc]), 1e-3 * np.abs(ref).max()), p
+
+
+def test_full_size_cfg4_gradient_tiled_equals_untiled():
+    """256^3 so 8, 1000 steps, 256 receivers, checkpoint every 50: the gradient in
+    the benchmark's launch configuration equals the untiled one bit for bit."""
+    import bench
+
+    cs = bench.workload("cfg4", device=DEV)
+    vtrue = synth.blob_velocity(cs["v"], amp=0.05, width_frac=1.0 / 16.0)
+    d_obs = api.forward(vtrue, cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
+                        sponge=cs["sponge"], vref=cs["vref"], **bench.launch_options("cfg4"))["rec"]
+    res = []
+    for opt in (dict(variant=L.FD_VARIANT_NAIVE), bench.launch_options("cfg4")):
+        J, g, _ = api.gradient(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
+                               d_obs, sponge=cs["sponge"], vref=cs["vref"], ckpt_every=50, **opt)
+        res.append((J, g))
+    assert res[0][0] == res[1][0] and res[0][0] > 0
+    assert torch.equal(res[0][1], res[1][1])
+    assert float(res[0][1].abs().max()) > 0
+
+
 def test_full_size_sampled_points_match_oracle():
     """256^3 so 8 at the benchmark's launch configuration: a Gaussian initial state
     advanced 12 steps; single points are checked against the oracle run on the
