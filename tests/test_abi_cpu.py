@@ -162,3 +162,16 @@ def test_gradient_and_adjoint_validate_on_host():
 def test_batch_rejects_bad_arguments():
     assert L.fd_forward_batch(-1, None, None, 0, 0, None) == L.FD_EINVAL
     assert L.fd_batch_workspace_size(0, None, L.FD_OP_FORWARD) == 0
+
+
+def test_plane_size_limit():
+    """One (y, z) plane of the internal layout (z rows padded to 32 floats) must
+    stay below 2^28 points: kernels address a plane with 32-bit byte offsets of
+    FP64 elements and mark outside points with offset 2^31."""
+    t = L.make_time(4, 1e-4)
+    ok = _grid((2, 16384, 16352))      # 16384 x 16352 < 2^28 (16352 is a multiple of 32)
+    assert L.fd_workspace_size(C.byref(ok), C.byref(t), None, None, None, L.FD_OP_GRADIENT) > 0
+    for shape in [(2, 16384, 16384), (2, 16384, 16353)]:   # 2^28, and 16353 pads to 16384
+        bad = _grid(shape)
+        assert L.fd_workspace_size(C.byref(bad), C.byref(t), None, None, None, L.FD_OP_FORWARD) == 0
+        assert _call_forward(bad, t, ws=C.c_void_p(0x10000), ws_bytes=1 << 40) == L.FD_EINVAL

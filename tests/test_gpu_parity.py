@@ -163,6 +163,24 @@ def test_all_configs_bit_identical_to_untiled(shape, so):
         assert ok, f"{opt} differs: max |du| {float((out['u'] - base['u']).abs().max())}"
 
 
+@pytest.mark.parametrize("shape,so", [((3, 5, 7), 8), ((1, 40, 33), 4), ((70, 1, 1), 8), ((2, 130, 3), 16),
+                                      ((5, 300), 16), ((9,), 16), ((1, 1, 1), 2)])
+def test_degenerate_grids_match_oracle_and_variants_agree(shape, so):
+    """Grids thinner than the stencil radius and unit extents: points outside
+    the grid are zero, so every configuration still matches the oracle and the
+    untiled kernel."""
+    cs = make_case(shape, so, 17, 0, nrec=2)
+    ref = oracle_forward(cs)
+    base = gpu_forward(cs, variant=L.FD_VARIANT_NAIVE)
+    err = rel_l2(base["u"].cpu().numpy(), ref["u"])
+    assert err <= 1e-5, err
+    assert rel_l2(base["rec"].cpu().numpy(), ref["rec"]) <= 1e-5
+    opts = [dict()] + (configs_for(so, small_chunk=1)[1:] if len(shape) == 3 else [])
+    for opt in opts:
+        out = gpu_forward(cs, **opt)
+        assert torch.equal(out["u"], base["u"]) and torch.equal(out["rec"], base["rec"]), opt
+
+
 def test_full_size_cfg2_tiled_equals_untiled():
     """256^3, so 8, 500 steps, smoothed random v, 15 Hz Ricker at depth 20, 20-cell sponge."""
     import bench
