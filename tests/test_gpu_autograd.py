@@ -59,7 +59,7 @@ def test_autograd_velocity_gradient_matches_oracle_vjp():
     got = vd.grad.cpu().numpy()
     err = np.linalg.norm(got - gref) / np.linalg.norm(gref)
     print(f"vjp vs oracle rel_l2 {err:.3e}")
-    assert err <= 2e-5
+    assert err <= 1e-5
 
 
 def test_autograd_wavelet_gradient_finite_difference():

@@ -355,7 +355,9 @@ def gradient_case():
     return cs, d_obs
 
 
-GRAD_TOL = 2e-4  # FP32 wavefields: the residual is a 5 % difference of two traces
+# gradients are required to rel-L2 1e-5 of the FP64 oracle (measured 6.7e-6 here: FP32 wavefields, and
+# the residual is a 5 % difference of two traces, which amplifies their rounding)
+GRAD_TOL = 1e-5
 
 
 def test_gradient_matches_oracle():
