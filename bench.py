@@ -87,7 +87,7 @@ def workload(name, device="cuda"):
 TUNED = {
     "cfg2": dict(variant=2, tile=(32, 32, 4)),
     "cfg2_t2": dict(variant=3, tblock=2, tile=(64, 32, 2)),
-    "cfg3": dict(variant=2, tile=(64, 16, 4)),
+    "cfg3": dict(variant=2, tile=(128, 16, 4)),
     "cfg3_t2": dict(variant=3, tblock=2, tile=(64, 32, 4)),
     "cfg4": dict(variant=2, tile=(32, 32, 4)),
 }

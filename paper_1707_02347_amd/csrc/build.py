@@ -78,6 +78,9 @@ def generate():
     path = os.path.join(GEN, "fd_registry.hip")
     _write_if_changed(path, "\n".join(reg))
     paths.append(path)
+    for f in os.listdir(GEN):  # sources of configurations no longer listed
+        if f.startswith("kEntry_") and os.path.join(GEN, f) not in paths:
+            os.remove(os.path.join(GEN, f))
     return paths
 
 
@@ -91,10 +94,21 @@ def _compile(src: str) -> str:
     deps = [src] + [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".h")]
     if os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps):
         return obj
+    kernel = os.path.basename(src).startswith("kEntry")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    if kernel:
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    if kernel:
+        # a sweep kernel that spills registers to scratch memory is far slower
+        # than any compiled alternative: refuse to ship it
+        spills = [int(m) for m in re.findall(r"ScratchSize \[bytes/lane\]: (\d+)", r.stderr)]
+        if any(spills):
+            os.remove(obj)
+            raise RuntimeError(f"{os.path.basename(src)}: kernel uses {max(spills)} bytes of scratch "
+                               "per lane (register spills); drop or change this configuration")
     return obj
 
 
