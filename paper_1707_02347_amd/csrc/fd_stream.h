@@ -282,10 +282,24 @@ struct StreamKernel {
         th.iend = th.xend + T * M;
         const int64_t N = (int64_t)a.nx * a.sxy;
 
-        Pre pf[NS];  // slot (i - ibeg) mod NS holds the loads of iteration i
+        // The first 2M iterations would only fill level 1's queue (no level
+        // computes a plane it needs before then): load those 2M head planes at
+        // once, all in flight together, and start the loop behind them.  The
+        // queue then holds, before the first push, planes istart - 2M - 1 + j
+        // in logical entries j = 1 .. 2M (entry 0 is never read).
+        const int istart = ibeg + 2 * M;
 #pragma unroll
-        for (int d = 0; d < ((NS > 1) ? NS - 1 : 1); ++d) load(a, th, pf[d], ibeg + d);
-        for (int i0 = ibeg; i0 < th.iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, N);
+        for (int j = 0; j < 2 * M; ++j) {
+            const int ph = plane(th, ibeg + j);
+            const auto rh = plane_rsrc(a.u0, ph, a.sxy, (unsigned)ph < (unsigned)a.nx);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) qu[0][r][pjb<0>(j + 1)] = bload(rh, th.bo[r]);
+        }
+
+        Pre pf[NS];  // slot (i - istart) mod NS holds the loads of iteration i
+#pragma unroll
+        for (int d = 0; d < ((NS > 1) ? NS - 1 : 1); ++d) load(a, th, pf[d], istart + d);
+        for (int i0 = istart; i0 < th.iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, N);
     }
 
     // Iterations i0 + PH .. i0 + UNROLL - 1 of the x loop (one per phase).  Each
