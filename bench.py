@@ -154,6 +154,34 @@ def _timed(fn, reps, warmup):
     return float(np.median(t)), float(t.mean()), float(t.std())
 
 
+def streaming_ceiling(field_mib, reps=30):
+    """Rate of a plain elementwise kernel with the sweep's access pattern --
+    three arrays read, one written in place over one of them
+    (b = a + b * c) -- on fields of the given size: the practical memory
+    ceiling for that footprint (the 256 MB Infinity Cache holds three
+    64 MiB fields, not three 512 MiB ones).  Returns TB/s of counted bytes."""
+    import torch
+
+    n = field_mib * 2 ** 20 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.ones(n, device="cuda")
+    c = torch.full((n,), 0.5, device="cuda")
+    for _ in range(3):
+        torch.addcmul(a, b, c, out=b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.addcmul(a, b, c, out=b)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del a, b, c
+    torch.cuda.empty_cache()
+    return round(4 * n * 4 / t / 1e12, 2)
+
+
 def time_sweeps(cs, opts, steps, warmup):
     """Median / mean / std ms of whole sweeps (HIP events on the launch stream)."""
     return _timed(lambda: _sweep(cs, opts), steps, warmup)
@@ -387,6 +415,9 @@ def main():
             "kernel": f"k_stream<M=4,T={T},PY={cfg_used['tile'][2]},NW={cfg_used['tile'][1] // cfg_used['tile'][2]}>",
             "avg_launch_us": round(kern_ms * 1e3, 2), "launches": launches, "bytes_per_launch": bytes_per_launch,
             "bytes_per_point": 20 if T >= 2 else 16}
+    ceil64 = streaming_ceiling(64)
+    roof["streaming_ceiling_tbs_64mib_fields"] = ceil64
+    roof["frac_of_streaming_ceiling"] = round(achieved / (ceil64 * 1000.0), 4)
     line = {
         "metric": METRIC,
         "value": round(res["tiled"]["gpts"], 2),
@@ -423,6 +454,7 @@ def main():
             r3[k] = round(n3 * c3["nt"] / (med * 1e-3) / 1e9, 2)
         line["cfg3_512cube_so16_gpts"] = r3
         line["cfg3_bw_equiv_frac_16B"] = round(r3["tiled"] * 16 / HBM_PEAK_GBS, 4)
+        line["cfg3_streaming_ceiling_tbs_512mib_fields"] = streaming_ceiling(512, reps=10)
         del c3
         torch.cuda.empty_cache()
         print("# time blocking at 512^3", file=sys.stderr, flush=True)
