@@ -34,6 +34,8 @@ FD_FLAG_NO_CFL_CHECK = 1
 FD_FLAG_CHECK_FINITE = 2
 FD_FLAG_NO_XCD_REMAP = 4
 FD_FLAG_NO_X_ALTERNATE = 8
+FD_FLAG_LOADS_STREAM = 16
+FD_FLAG_LOADS_KEEP = 32
 
 FD_OP_FORWARD = 0
 FD_OP_ADJOINT = 1

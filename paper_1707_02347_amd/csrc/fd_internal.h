@@ -84,6 +84,9 @@ struct SweepArgs {
     // neighbouring chunks both read are read at the same time (both at the
     // chunks' ends or both at their starts).
     int alt;
+    // ntl != 0: u^{n-1}, q and the gradient fields are loaded non-temporally
+    // (single-pass launches; a grouped launch takes the policy as an argument).
+    int ntl;
 };
 
 enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
@@ -116,8 +119,8 @@ struct KernelKey {
 // tiles of `a`; otherwise it walks the `total` tiles of the nlist entries
 // with `grid` workgroups, persistently if grid < total (iso selects the Laplacian form).
 bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
-bool launch_stream_grouped(const KernelKey &key, bool iso, const GroupEntry *list, int nlist,
-                           int total, int grid, hipStream_t s);
+bool launch_stream_grouped(const KernelKey &key, bool iso, bool ntl, const GroupEntry *list,
+                           int nlist, int total, int grid, hipStream_t s);
 // Resident workgroups per CU of a configuration's single-pass or grouped kernel
 // (0 if not compiled).
 int stream_occupancy(const KernelKey &key, bool iso, bool grouped);

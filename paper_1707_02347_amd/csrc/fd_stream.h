@@ -66,16 +66,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field,
                                              valid ? (int)(uint32_t)(sxy * 4) : 0, 0x00020000);
 }
 
+// Cache policy of a buffer access (the instruction's cache-policy bits):
+// kKeep for data that other workgroups or the next step read again soon,
+// kStream (non-temporal) for data touched once per step.  Non-temporal stores
+// of the new field are faster at every size measured; non-temporal loads of
+// u^{n-1} and q only when the fields do not fit the Infinity Cache (they keep
+// q from staying there for the next step).
+constexpr int kKeep = 0;
+constexpr int kStream = 2;
+
+template <int CP = kKeep>
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
 {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, CP));
 }
 
 // Buffer store: dropped by the hardware when byte_off is beyond the resource's
 // range, so a store for a point outside the output needs no branch.
+template <int CP = kKeep>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)byte_off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)byte_off, 0, CP);
 }
 
 // Resource over `nbytes` bytes at `base` (an empty range if !valid).
@@ -86,20 +97,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, in
                                              valid ? (int)(uint32_t)nbytes : 0, 0x00020000);
 }
 
+template <int CP = kKeep>
 __device__ __forceinline__ double bload64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, CP));
 }
 
+template <int CP = kKeep>
 __device__ __forceinline__ void bstore64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, double v)
 {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)byte_off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)byte_off, 0, CP);
 }
 
-template <int M, int T, int PY, int NW, int MODE, bool ISO>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
 struct StreamKernel {
     using G = Geo<M, T, PY, NW>;
+    // cache policy of the loads each point needs once per step (u^{n-1}, q,
+    // and the gradient fields)
+    static constexpr int LP = NTL ? kStream : kKeep;
     // Register queues along x.  Short queues (M <= 4) rotate by renaming: the
     // x loop is unrolled by QS (the queue length 2M + 1 rounded up to a
     // multiple of NS below) and the slot of logical entry j (0 = oldest,
@@ -435,13 +451,13 @@ struct StreamKernel {
         for (int s = 0; s < G::HS; ++s) P.halo[s] = bload(rc, th.hb[s]);
         const auto rm = plane_rsrc(a.um, c1, a.sxy, l1);
 #pragma unroll
-        for (int r = 0; r < PY; ++r) P.up1[r] = bload(rm, th.bo[r]);
+        for (int r = 0; r < PY; ++r) P.up1[r] = bload<LP>(rm, th.bo[r]);
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int ct = plane(th, i - t * M);
             const auto rq = plane_rsrc(a.q, ct, a.sxy, needed(a, th, t, ct));
 #pragma unroll
-            for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload(rq, th.bo[r]);
+            for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload<LP>(rq, th.bo[r]);
         }
         if constexpr (IMG) {
             // only planes this chunk owns are read (and later written); offsets
@@ -449,7 +465,7 @@ struct StreamKernel {
             const bool o1 = c1 >= th.x0 && c1 < th.xend;
             const auto rg = span_rsrc(a.g + (int64_t)(o1 ? c1 : 0) * a.sxy, a.sxy * 8, o1);
 #pragma unroll
-            for (int r = 0; r < PY; ++r) P.g[r] = bload64(rg, out_off64(th, r));
+            for (int r = 0; r < PY; ++r) P.g[r] = bload64<LP>(rg, out_off64(th, r));
             const int64_t N = (int64_t)a.nx * a.sxy;
 #pragma unroll
             for (int t = 1; t <= T; ++t) {
@@ -459,7 +475,7 @@ struct StreamKernel {
                                   (int64_t)(ot ? ct : 0) * a.sxy;
                 const auto rd = span_rsrc(dp, a.sxy * 4, ot);
 #pragma unroll
-                for (int r = 0; r < PY; ++r) P.d2[t - 1][r] = bload(rd, out_off(th, r));
+                for (int r = 0; r < PY; ++r) P.d2[t - 1][r] = bload<LP>(rd, out_off(th, r));
             }
         }
     }
@@ -588,7 +604,7 @@ struct StreamKernel {
                 float um;
                 if constexpr (t == 1) um = P.up1[r];
                 else um = qu[t - 2][r][pj<PH>(0)];
-                bstore(rd, out_off(th, r), fmaf(-2.0f, qu[t - 1][r][pj<PH>(M)], out[r]) + um);
+                bstore<kStream>(rd, out_off(th, r), fmaf(-2.0f, qu[t - 1][r][pj<PH>(M)], out[r]) + um);
             }
         }
         if constexpr (MODE == kImaging) {
@@ -602,7 +618,7 @@ struct StreamKernel {
                 if constexpr (t == 1) base = P.g[r];
                 else base = acc[r][J];
                 const double nv = fma((double)out[r], (double)P.d2[t - 1][r], base);
-                if constexpr (t == T) bstore64(rg, out_off64(th, r), nv);
+                if constexpr (t == T) bstore64<LP>(rg, out_off64(th, r), nv);
                 else acc[r][J] = nv;
             }
         }
@@ -612,11 +628,11 @@ struct StreamKernel {
             const bool outp = xin && own;
             const auto r1 = plane_rsrc(a.o1, c, a.sxy, outp);
 #pragma unroll
-            for (int r = 0; r < PY; ++r) bstore(r1, out_off(th, r), out[r]);
+            for (int r = 0; r < PY; ++r) bstore<kStream>(r1, out_off(th, r), out[r]);
             if constexpr (T >= 2) {
                 const auto r2 = plane_rsrc(a.o2, c, a.sxy, outp);
 #pragma unroll
-                for (int r = 0; r < PY; ++r) bstore(r2, out_off(th, r), qu[T - 1][r][pj<PH>(M)]);
+                for (int r = 0; r < PY; ++r) bstore<kStream>(r2, out_off(th, r), qu[T - 1][r][pj<PH>(M)]);
             }
         } else {
 #pragma unroll
@@ -628,10 +644,10 @@ struct StreamKernel {
 
 // One pass of one shot: workgroup b runs tile b (arguments by value, so every
 // field lives in scalar registers or the kernel-argument segment).
-template <int M, int T, int PY, int NW, int MODE, bool ISO>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
 __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 {
-    using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL>;
     __shared__ typename K::Smem sm;
     K::run(a, sm, blockIdx.x, gridDim.x);
 }
@@ -642,11 +658,11 @@ __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 // grid is a multiple of 8, the items of one round are dealt so that each XCD
 // takes a contiguous block of them (neighbouring tiles of one shot share that
 // XCD's L2).
-template <int M, int T, int PY, int NW, int MODE, bool ISO>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
 __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__restrict__ list,
                                                             int nlist, int total)
 {
-    using K = StreamKernel<M, T, PY, NW, MODE, ISO>;
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL>;
     __shared__ typename K::Smem sm;
     const int b = blockIdx.x;
     const int first = ((gridDim.x & 7) == 0) ? (b & 7) * (gridDim.x >> 3) + (b >> 3) : b;
@@ -671,36 +687,57 @@ __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__
     }
 }
 
-// Launch helpers shared by the generated entry files.
+// Launch helpers shared by the generated entry files.  The non-temporal-load
+// form (a.ntl, or ntl for a grouped launch) differs from the other only in
+// cache-policy bits, so both give identical results.
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
+void issue_stream(const SweepArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (a.ntl)
+        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, false>), grid, block, 0, s, a);
+}
+
 template <int M, int T, int PY, int NW, int MODE, int F>
 bool entry_launch(const SweepArgs &a, hipStream_t s)
 {
     const dim3 grid(a.ntz * a.nty * a.ntx), block(64 * NW);
     if (a.w.iso) {
-        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, true>), grid, block, 0, s, a);
+        issue_stream<M, T, PY, NW, MODE, true>(a, grid, block, s);
         return true;
     }
     if constexpr ((F & 1) != 0) {
-        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, false>), grid, block, 0, s, a);
+        issue_stream<M, T, PY, NW, MODE, false>(a, grid, block, s);
         return true;
     }
     return false;
 }
 
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
+void issue_grouped(bool ntl, const GroupEntry *list, int nlist, int total, dim3 grid, dim3 block,
+                    hipStream_t s)
+{
+    if (ntl)
+        hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, true>), grid, block, 0, s,
+                           list, nlist, total);
+    else
+        hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, false>), grid, block, 0, s,
+                           list, nlist, total);
+}
+
 template <int M, int T, int PY, int NW, int MODE, int F>
-bool entry_launch_group(bool iso, const GroupEntry *list, int nlist, int total, int grid,
-                        hipStream_t s)
+bool entry_launch_group(bool iso, bool ntl, const GroupEntry *list, int nlist, int total,
+                        int grid, hipStream_t s)
 {
     if constexpr ((F & 2) != 0) {
         const dim3 g(grid), block(64 * NW);
         if (iso) {
-            hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, true>), g, block, 0, s, list,
-                               nlist, total);
+            issue_grouped<M, T, PY, NW, MODE, true>(ntl, list, nlist, total, g, block, s);
             return true;
         }
         if constexpr ((F & 1) != 0) {
-            hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, false>), g, block, 0, s, list,
-                               nlist, total);
+            issue_grouped<M, T, PY, NW, MODE, false>(ntl, list, nlist, total, g, block, s);
             return true;
         }
     }
@@ -708,7 +745,8 @@ bool entry_launch_group(bool iso, const GroupEntry *list, int nlist, int total, 
 }
 
 // Resident workgroups per CU of the single-pass or the grouped kernel (0 if the
-// requested form is not compiled).
+// requested form is not compiled).  Both cache-policy forms use the same
+// registers and LDS.
 template <int M, int T, int PY, int NW, int MODE, int F>
 int entry_occupancy(bool iso, bool grouped)
 {
@@ -717,14 +755,15 @@ int entry_occupancy(bool iso, bool grouped)
     const void *fn = nullptr;
     if (grouped) {
         if constexpr ((F & 2) != 0) {
-            if (iso) fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true>);
+            if (iso)
+                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true, false>);
             else if constexpr ((F & 1) != 0)
-                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false>);
+                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false, false>);
         }
     } else {
-        if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true>);
+        if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true, false>);
         else if constexpr ((F & 1) != 0)
-            fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, false>);
+            fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, false, false>);
     }
     if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * NW, 0);
     return e == hipSuccess ? n : 0;

@@ -144,6 +144,9 @@ def test_unsupported_tile_is_reported():
     assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
     o = L.make_options(flags=1 << 7)  # not an FD_FLAG_*
     assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
+    # the two cache-policy flags exclude each other
+    o = L.make_options(flags=L.FD_FLAG_LOADS_STREAM | L.FD_FLAG_LOADS_KEEP)
+    assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
 
 
 def test_gradient_and_adjoint_validate_on_host():
