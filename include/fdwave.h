@@ -94,10 +94,11 @@ extern "C" {
 #define FD_FLAG_NO_X_ALTERNATE 8u /* stream every x-chunk upward (for A/B timing) */
 /* Cache policy of the loads each point makes once per step (u^{n-1}, the
  * coefficient field q, and the gradient's fields).  By default they are
- * non-temporal when the fields a step re-reads (u^n, u^{n-1}, q; the FP64
- * image of a gradient) exceed 320 MiB, the share the GPU's last-level cache
- * keeps, and ordinary otherwise; for a grouped batch launch the fields of all
- * its shots count.  The two flags force one policy (for A/B timing); setting
+ * non-temporal in single-step passes when the fields a step re-reads (u^n,
+ * u^{n-1}, q; the FP64 image of a gradient) exceed 320 MiB, the share the
+ * GPU's last-level cache keeps, and ordinary otherwise (time-blocked passes
+ * share those loads between overlapping tiles); for a grouped batch launch
+ * the fields of all its shots count.  The two flags force one policy (for A/B timing); setting
  * both is FD_EINVAL.  Results are identical either way. */
 #define FD_FLAG_LOADS_STREAM 16u
 #define FD_FLAG_LOADS_KEEP 32u

@@ -61,10 +61,13 @@ double resident_bytes(const SweepArgs &a, int mode)
 // 7 % faster at 512^3.
 constexpr double kCacheKeeps = 320.0 * 1048576.0;
 
-// loads: -1 automatic, 0 ordinary, 1 non-temporal.
-bool stream_loads(int loads, double resident)
+// loads: -1 automatic, 0 ordinary, 1 non-temporal.  Automatic is ordinary for
+// time-blocked passes: their overlapped tiles load u^{n-1} and q around the
+// output tile, and the neighbouring tiles find those lines in L2 (512^3, so 2,
+// T = 4: 464 GPts/s ordinary, 371 non-temporal).
+bool stream_loads(int loads, double resident, int T)
 {
-    return loads >= 0 ? loads != 0 : resident > kCacheKeeps;
+    return loads >= 0 ? loads != 0 : (T == 1 && resident > kCacheKeeps);
 }
 
 int stream_occupancy(const KernelKey &k, bool iso, bool grouped)
@@ -890,7 +893,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.ntx = (d.nx + a.lx - 1) / a.lx;
         a.remap = c.plan.remap ? 1 : 0;
         a.alt = c.plan.alt ? 1 : 0;
-        a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode)) ? 1 : 0;
+        a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
         supertile(k, a);
         c.ex.pass(k, a, c.plan.loads);
         if (Tk == 1) swap_in(st, o1, st.cur);
@@ -1632,7 +1635,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
             L.grid = L.total;
             // the shots of one grouped launch stream side by side: their fields
             // compete for the cache together
-            L.ntl = stream_loads(lead.loads, resident);
+            L.ntl = stream_loads(lead.loads, resident, lead.key.T);
             plan.push_back(L);
         }
     }
