@@ -50,6 +50,8 @@ class _Problem(C.Structure):
         ("nr", C.c_int32),
         ("src", C.POINTER(C.c_int32)),
         ("rec", C.POINTER(C.c_int32)),
+        ("spos", C.POINTER(C.c_double)),
+        ("rpos", C.POINTER(C.c_double)),
     ]
 
 
@@ -102,9 +104,10 @@ class Problem:
         self.h = tuple(float(x) for x in hh)
         self.so, self.nt, self.dt = int(so), int(nt), float(dt)
         self.sponge, self.vref = int(sponge), float(vref)
-        empty = np.zeros((0, self.ndim), dtype=np.int32)
-        self.src = np.ascontiguousarray(empty if src is None else np.asarray(src, dtype=np.int32)).reshape(-1, self.ndim)
-        self.rec = np.ascontiguousarray(empty if rec is None else np.asarray(rec, dtype=np.int32)).reshape(-1, self.ndim)
+        # integer arrays are grid indices; floating-point arrays are positions in
+        # grid-index units (off the grid, multilinear interpolation)
+        self.src, self.spos = self._points(src)
+        self.rec, self.rpos = self._points(rec)
         s = _Problem()
         s.ndim, s.so = self.ndim, self.so
         for a in range(3):
@@ -115,7 +118,18 @@ class Problem:
         s.ns, s.nr = len(self.src), len(self.rec)
         s.src = self.src.ctypes.data_as(C.POINTER(C.c_int32))
         s.rec = self.rec.ctypes.data_as(C.POINTER(C.c_int32))
+        s.spos = None if self.spos is None else _dptr(self.spos)
+        s.rpos = None if self.rpos is None else _dptr(self.rpos)
         self._s = s
+
+    def _points(self, pts):
+        if pts is None:
+            return np.zeros((0, self.ndim), dtype=np.int32), None
+        a = np.asarray(pts)
+        if np.issubdtype(a.dtype, np.floating):
+            pos = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, self.ndim)
+            return np.zeros((len(pos), self.ndim), dtype=np.int32), pos
+        return np.ascontiguousarray(a, dtype=np.int32).reshape(-1, self.ndim), None
 
     @property
     def npts(self):

@@ -24,6 +24,13 @@
  *   * point source injection in the step that produces u^{n+1}:
  *       u^{n+1}(s) += 2 dt^2 w[n][s] / (dt*damp(s) + 2 m(s))
  *   * receivers sample the new level on grid nodes: d[n][r] = u^{n+1}(r)
+ *   * a point off the grid (a position in grid-index units, p_a in [0, n_a - 1])
+ *     acts through multilinear interpolation: P is the row of weights
+ *     w_c = prod_a (c_a ? f_a : 1 - f_a) over the 2^d nodes c of the cell that
+ *     holds it (f_a the fractional part; on the last node of an axis the cell
+ *     below is used).  A receiver records P u^{n+1}; a source adds
+ *     A^{-1} 2 dt^2 P^T w, i.e. w_c 2 dt^2 w / (dt*damp(c) + 2 m(c)) at each node
+ *     (the definitions above are the special case of a single node, weight 1).
  *   * separable sponge: damp(i) = sum_a d0_a (delta_a / L)^2, delta_a the number
  *     of cells into the outer L-cell layer (0 in the interior and at its inner
  *     edge), d0_a = 1.5 ln(1000) / (vref L h_a).  damp carries the units of m
@@ -64,9 +71,18 @@ typedef struct or_problem {
     const double *v;     /* velocity, N^d (m/s) */
     int32_t ns;          /* number of sources */
     int32_t nr;          /* number of receivers */
-    const int32_t *src;  /* [ns][ndim] grid indices */
-    const int32_t *rec;  /* [nr][ndim] grid indices */
+    const int32_t *src;  /* [ns][ndim] grid indices (used when spos is NULL) */
+    const int32_t *rec;  /* [nr][ndim] grid indices (used when rpos is NULL) */
+    const double *spos;  /* [ns][ndim] positions in grid-index units, or NULL */
+    const double *rpos;  /* [nr][ndim] positions in grid-index units, or NULL */
 } or_problem;
+
+/* The nodes a point acts on and their interpolation weights (at most 8). */
+typedef struct stencil_pt {
+    int n;
+    int64_t idx[8];
+    double w[8];
+} stencil_pt;
 
 typedef struct geom {
     int64_t n[3];   /* extents as 3-D (leading unit axes for ndim < 3) */
@@ -223,12 +239,78 @@ static void leapfrog_step(const geom *g, const double *c, int M, double dt,
             }
 }
 
+/* Multilinear interpolation of a position: the nodes of its cell with nonzero
+ * weight.  -1 if a coordinate is not finite or lies outside [0, n_a - 1]. */
+static int point_stencil(const or_problem *p, const geom *g, const double *pos, stencil_pt *out)
+{
+    int64_t base[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < p->ndim; ++a) {
+        double x = pos[a];
+        int64_t n = p->n[a];
+        if (!(x >= 0.0) || !(x <= (double)(n - 1))) return -1;
+        int64_t i = (int64_t)floor(x);
+        if (i > n - 2) i = n - 2; /* the last node: the cell below, fraction 1 */
+        if (i < 0) i = 0;         /* an axis of one node: fraction 0 */
+        base[a + g->first] = i;
+        f[a + g->first] = x - (double)i;
+    }
+    out->n = 0;
+    for (int c = 0; c < 8; ++c) {
+        double w = 1.0;
+        int64_t ii[3];
+        for (int a = 0; a < 3; ++a) {
+            int bit = (c >> (2 - a)) & 1;
+            if (a < g->first && bit) { w = 0.0; break; }
+            ii[a] = base[a] + bit;
+            w *= bit ? f[a] : 1.0 - f[a];
+        }
+        if (w == 0.0) continue;
+        out->idx[out->n] = (ii[0] * g->n[1] + ii[1]) * g->n[2] + ii[2];
+        out->w[out->n] = w;
+        out->n++;
+    }
+    return 0;
+}
+
+/* The stencil of point k of a set: one node of weight 1 for grid indices. */
+static int set_stencil(const or_problem *p, const geom *g, const int32_t *idx, const double *pos,
+                       int k, stencil_pt *out)
+{
+    if (pos) return point_stencil(p, g, pos + (int64_t)k * p->ndim, out);
+    int64_t i = point_index(p, g, idx + (int64_t)k * p->ndim);
+    if (i < 0) return -1;
+    out->n = 1;
+    out->idx[0] = i;
+    out->w[0] = 1.0;
+    return 0;
+}
+
+/* P u: the value a receiver (or an adjoint source sample) reads. */
+static double sample(const stencil_pt *s, const double *u)
+{
+    double acc = 0.0;
+    for (int j = 0; j < s->n; ++j) acc += s->w[j] * u[s->idx[j]];
+    return acc;
+}
+
+/* u += A^{-1} P^T a: an amplitude a (already multiplied by its time factor)
+ * spread over the point's nodes, each divided by its own 2m + dt damp. */
+static void spread(const stencil_pt *s, double a, double dt, const double *m, const double *damp,
+                   double *u)
+{
+    for (int j = 0; j < s->n; ++j) {
+        int64_t i = s->idx[j];
+        u[i] += s->w[j] * a / (dt * damp[i] + 2.0 * m[i]);
+    }
+}
+
 typedef struct work {
     geom g;
     double c[OR_MAXM + 1];
     int M;
     double *m, *damp;
-    int64_t *sidx, *ridx;
+    stencil_pt *sp, *rp;
 } work;
 
 static int work_init(const or_problem *p, work *w)
@@ -241,18 +323,18 @@ static int work_init(const or_problem *p, work *w)
     int64_t N = w->g.npts;
     w->m = (double *)malloc(sizeof(double) * N);
     w->damp = (double *)malloc(sizeof(double) * N);
-    w->sidx = (int64_t *)malloc(sizeof(int64_t) * (p->ns > 0 ? p->ns : 1));
-    w->ridx = (int64_t *)malloc(sizeof(int64_t) * (p->nr > 0 ? p->nr : 1));
-    if (!w->m || !w->damp || !w->sidx || !w->ridx) return -2;
+    w->sp = (stencil_pt *)malloc(sizeof(stencil_pt) * (p->ns > 0 ? p->ns : 1));
+    w->rp = (stencil_pt *)malloc(sizeof(stencil_pt) * (p->nr > 0 ? p->nr : 1));
+    if (!w->m || !w->damp || !w->sp || !w->rp) return -2;
     for (int64_t i = 0; i < N; ++i) {
         if (!(p->v[i] > 0)) return -1;
         w->m[i] = 1.0 / (p->v[i] * p->v[i]);
     }
     damp_g(p, &w->g, w->damp);
     for (int s = 0; s < p->ns; ++s)
-        if ((w->sidx[s] = point_index(p, &w->g, p->src + (int64_t)s * p->ndim)) < 0) return -3;
+        if (set_stencil(p, &w->g, p->src, p->spos, s, &w->sp[s])) return -3;
     for (int r = 0; r < p->nr; ++r)
-        if ((w->ridx[r] = point_index(p, &w->g, p->rec + (int64_t)r * p->ndim)) < 0) return -3;
+        if (set_stencil(p, &w->g, p->rec, p->rpos, r, &w->rp[r])) return -3;
     return 0;
 }
 
@@ -260,8 +342,8 @@ static void work_free(work *w)
 {
     free(w->m);
     free(w->damp);
-    free(w->sidx);
-    free(w->ridx);
+    free(w->sp);
+    free(w->rp);
 }
 
 /*
@@ -287,12 +369,10 @@ int or_forward(const or_problem *p, const double *amp, double *rec_out,
     for (int64_t n = 0; n < p->nt; ++n) {
         leapfrog_step(&w.g, w.c, w.M, p->dt, w.m, w.damp, u_cur, u_prev, u_new);
         if (amp)
-            for (int s = 0; s < p->ns; ++s) {
-                int64_t i = w.sidx[s];
-                u_new[i] += 2.0 * dt2 * amp[n * p->ns + s] / (p->dt * w.damp[i] + 2.0 * w.m[i]);
-            }
+            for (int s = 0; s < p->ns; ++s)
+                spread(&w.sp[s], 2.0 * dt2 * amp[n * p->ns + s], p->dt, w.m, w.damp, u_new);
         if (rec_out)
-            for (int r = 0; r < p->nr; ++r) rec_out[n * p->nr + r] = u_new[w.ridx[r]];
+            for (int r = 0; r < p->nr; ++r) rec_out[n * p->nr + r] = sample(&w.rp[r], u_new);
         /* rotate: prev <- cur, cur <- new */
         memcpy(u_prev, u_cur, sizeof(double) * N);
         memcpy(u_cur, u_new, sizeof(double) * N);
@@ -324,12 +404,9 @@ static int adjoint_w(const or_problem *p, work *w, const double *y, double *src_
     if (gm) memset(gm, 0, sizeof(double) * N);
     for (int64_t k = p->nt; k >= 1; --k) {
         leapfrog_step(&w->g, w->c, w->M, p->dt, w->m, w->damp, l1, l2, l0);
-        for (int r = 0; r < p->nr; ++r) {
-            int64_t i = w->ridx[r];
-            l0[i] += y[(k - 1) * p->nr + r] / (p->dt * w->damp[i] + 2.0 * w->m[i]);
-        }
+        for (int r = 0; r < p->nr; ++r) spread(&w->rp[r], y[(k - 1) * p->nr + r], p->dt, w->m, w->damp, l0);
         if (src_out)
-            for (int s = 0; s < p->ns; ++s) src_out[(k - 1) * p->ns + s] = 2.0 * dt2 * l0[w->sidx[s]];
+            for (int s = 0; s < p->ns; ++s) src_out[(k - 1) * p->ns + s] = 2.0 * dt2 * sample(&w->sp[s], l0);
         if (lam_hist) memcpy(lam_hist + (p->nt + 2 - k) * N, l0, sizeof(double) * N);
         if (gm && uhist) {
             /* uhist entry j holds u^{j-1}: u^k at j = k+1 */

@@ -149,6 +149,28 @@ def receiver_line(shape, nrec: int, depth: int = 20, cross: int | None = None) -
     return out
 
 
+def offgrid_points(shape, npts: int, seed: int = 1707, margin: float = 0.0) -> np.ndarray:
+    """``npts`` seeded positions in grid-index units (float64, [npts][ndim]), each
+    coordinate uniform in [margin, n_a - 1 - margin]: points between grid nodes."""
+    rng = np.random.default_rng(seed)
+    lo = np.full(len(shape), float(margin))
+    hi = np.array([float(n) - 1.0 - margin for n in shape])
+    return lo + (hi - lo) * rng.random((npts, len(shape)))
+
+
+def offgrid_receiver_line(shape, nrec: int, depth: float = 20.37, cross: float | None = None) -> np.ndarray:
+    """``nrec`` receivers evenly spaced along axis 0 between nodes (float64
+    positions), at axis-1 position ``cross`` (default: the middle plus 0.29 cell)
+    and depth ``depth`` along the last axis."""
+    n0 = float(shape[0])
+    out = np.zeros((nrec, len(shape)), dtype=np.float64)
+    out[:, 0] = 0.45 + np.arange(nrec, dtype=np.float64) * (n0 - 1.9) / max(nrec, 1)
+    if len(shape) == 3:
+        out[:, 1] = float(shape[1]) / 2.0 + 0.29 if cross is None else float(cross)
+    out[:, -1] = float(depth)
+    return out
+
+
 def shot_batch(nshots: int = 32, seed: int = 2347, nmin: int = 128, nmax: int = 320,
                orders=(4, 8, 16), ntmin: int = 500, ntmax: int = 1000):
     """Seeded uneven shot list: dicts with keys ``n`` (cubic side), ``so``, ``nt``, ``vseed``."""

@@ -23,10 +23,14 @@ MUTATIONS = {
     "transposed_index": ("return u[(i0 * g->n[1] + i1) * g->n[2] + i2];", "return u[(i1 * g->n[0] + i0) * g->n[2] + i2];"),
     "update_centre_factor": ("+ 4.0 * m[i] * u_cur[i] +", "+ 2.0 * m[i] * u_cur[i] +"),
     "damping_sign": ("u_new[i] = ((tcse - 2.0 * m[i]) * u_prev[i]", "u_new[i] = ((-tcse - 2.0 * m[i]) * u_prev[i]"),
-    "source_scale": ("u_new[i] += 2.0 * dt2 * amp[n * p->ns + s]", "u_new[i] += dt2 * amp[n * p->ns + s]"),
-    "receiver_old_level": ("rec_out[n * p->nr + r] = u_new[w.ridx[r]];", "rec_out[n * p->nr + r] = u_cur[w.ridx[r]];"),
-    "adjoint_injection_unscaled": ("l0[i] += y[(k - 1) * p->nr + r] / (p->dt * w->damp[i] + 2.0 * w->m[i]);",
-                                   "l0[i] += y[(k - 1) * p->nr + r];"),
+    "source_scale": ("spread(&w.sp[s], 2.0 * dt2 * amp[n * p->ns + s]", "spread(&w.sp[s], dt2 * amp[n * p->ns + s]"),
+    "receiver_old_level": ("sample(&w.rp[r], u_new);", "sample(&w.rp[r], u_cur);"),
+    "injection_unscaled": ("u[i] += s->w[j] * a / (dt * damp[i] + 2.0 * m[i]);", "u[i] += s->w[j] * a;"),
+    "adjoint_source_sample_unscaled": ("= 2.0 * dt2 * sample(&w->sp[s], l0);", "= dt2 * sample(&w->sp[s], l0);"),
+    "interp_fraction_swapped": ("w *= bit ? f[a] : 1.0 - f[a];", "w *= bit ? 1.0 - f[a] : f[a];"),
+    "interp_sample_unweighted": ("acc += s->w[j] * u[s->idx[j]];", "acc += u[s->idx[j]];"),
+    "interp_spread_unweighted": ("u[i] += s->w[j] * a / (dt * damp[i] + 2.0 * m[i]);", "u[i] += a / (dt * damp[i] + 2.0 * m[i]);"),
+    "interp_cell_above": ("base[a + g->first] = i;", "base[a + g->first] = i > 0 ? i - 1 : i;"),
     "imaging_first_difference": ("(uk[i] - 2.0 * uk1[i] + uk2[i])", "(uk[i] - uk1[i])"),
     "sponge_off_by_one": ("if (i < L) delta = (double)(L - i);", "if (i < L) delta = (double)(L - i - 1);"),
     "dt_squared_missing": ("double dt2 = dt * dt;\n#pragma omp parallel for schedule(static)\n    for (int64_t i0 = 0; i0 < g->n[0]; ++i0)\n        for (int64_t i1 = 0; i1 < g->n[1]; ++i1)\n            for (int64_t i2 = 0; i2 < g->n[2]; ++i2) {\n                int64_t i = (i0 * g->n[1] + i1) * g->n[2] + i2;\n                double tcse",
@@ -48,6 +52,9 @@ def _checks():
         yield lambda case=case: pins.test_forward_and_adjoint_equal_dense_space_time_solve(*case)
     yield lambda: pins.test_gradient_equals_complex_step_of_dense_system((6, 5), 4, 6, 1)
     yield lambda: pins.test_first_step_injection_and_receiver_sampling()
+    yield lambda: pins.test_offgrid_receivers_read_multilinear_fields_exactly(4)
+    yield lambda: pins.test_offgrid_source_spreads_unit_mass_at_its_position((4.25, 5.5, 6.75))
+    yield lambda: pins.test_offgrid_dot_product_fp64((40, 36))
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

@@ -441,3 +441,109 @@ def test_first_step_injection_and_receiver_sampling():
     for n in range(nt):
         for r, idx in enumerate(rec):
             assert out["rec"][n, r] == out["hist"][n + 2][tuple(idx)]
+
+
+# ---------------------------------------------------------------- points off the grid
+# A point between nodes acts through multilinear interpolation (the reading
+# adopted for the paper's unspecified source/receiver operators): a receiver
+# reads P u, a source adds A^{-1} 2 dt^2 P^T w.  The pins below use what
+# interpolation fixes on its own: it reproduces multilinear functions, its
+# weights sum to one and have their centre at the point, integer positions are
+# the grid indices, and forward and adjoint stay transposes.
+OFFGRID_REC = np.array([[4.25, 5.5, 6.75], [3.0, 7.125, 5.0], [6.5, 4.0, 4.0], [5.875, 2.0625, 8.5]])
+
+
+def _multilinear(x, y, z):
+    return 1.0 + 0.3 * x - 0.2 * y + 0.1 * z + 0.05 * x * y - 0.02 * y * z + 0.01 * x * z + 0.003 * x * y * z
+
+
+@pytest.mark.parametrize("so", [2, 4])
+def test_offgrid_receivers_read_multilinear_fields_exactly(so):
+    """u^0 = u^-1 = P with P multilinear: every stencil row sums to zero and P is
+    linear along each axis, so L_h P = 0 wherever the stencil stays on the grid and
+    u^1 = P there; interpolation then returns P at any point of such a cell."""
+    shape = (11, 12, 13)
+    X = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    P = _multilinear(*X)
+    prob = oracle.Problem(np.full(shape, 2000.0), [10.0, 12.0, 9.0], so, 1, 1e-3, rec=OFFGRID_REC)
+    out = oracle.forward(prob, u0=P, um1=P)
+    expect = np.array([_multilinear(*p) for p in OFFGRID_REC])
+    np.testing.assert_allclose(out["rec"][0], expect, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("pos", [(4.25, 5.5, 6.75), (0.0, 11.0, 3.4), (10.0, 0.6, 12.0), (7.0, 3.0, 2.0)])
+def test_offgrid_source_spreads_unit_mass_at_its_position(pos):
+    """From rest, one step with constant m and no sponge leaves dt^2 v^2 a times
+    the interpolation weights: nonnegative, summing to one, centred on the point
+    and confined to the nodes of its cell."""
+    shape, v, dt, a = (11, 12, 13), 2000.0, 1e-3, 1.7
+    prob = oracle.Problem(np.full(shape, v), [10.0] * 3, 4, 1, dt, src=np.array([pos]))
+    u1 = oracle.forward(prob, amp=np.array([[a]]))["u"]
+    mass = dt * dt * v * v * a
+    assert abs(u1.sum() - mass) <= 1e-14 * mass
+    assert u1.min() >= 0.0
+    X = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    for ax in range(3):
+        assert abs(float((u1 * X[ax]).sum()) / float(u1.sum()) - pos[ax]) <= 1e-12
+    support = np.argwhere(u1 != 0.0)
+    assert np.all(np.abs(support - np.array(pos)) < 1.0)
+    assert len(support) <= 8
+
+
+def test_integer_positions_equal_grid_indices():
+    shape, so, nt = (9, 8, 10), 4, 12
+    v = np.random.default_rng(5).uniform(1500, 4000, shape)
+    h, dt = [10.0, 12.0, 9.0], 1e-3
+    src = np.array([[1, 2, 3], [4, 4, 4]], dtype=np.int32)
+    rec = np.array([[1, 2, 3], [4, 4, 5], [8, 7, 9], [0, 0, 0]], dtype=np.int32)
+    w = np.random.default_rng(6).standard_normal((nt, 2))
+    y = np.random.default_rng(7).standard_normal((nt, 4))
+    a = oracle.Problem(v, h, so, nt, dt, sponge=2, vref=3000.0, src=src, rec=rec)
+    b = oracle.Problem(v, h, so, nt, dt, sponge=2, vref=3000.0, src=src.astype(np.float64),
+                       rec=rec.astype(np.float64))
+    fa, fb = oracle.forward(a, amp=w), oracle.forward(b, amp=w)
+    np.testing.assert_array_equal(fa["rec"], fb["rec"])
+    np.testing.assert_array_equal(fa["u"], fb["u"])
+    np.testing.assert_array_equal(oracle.adjoint(a, y)["src"], oracle.adjoint(b, y)["src"])
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 22), (40, 36)])
+def test_offgrid_dot_product_fp64(shape):
+    nt, so = 40, 8
+    v = synth.smooth_velocity(shape, seed=1709, sigma=3.0).numpy().astype(np.float64)
+    h = [10.0, 12.0, 9.0][:len(shape)]
+    dt = 0.8 * 0.4529 * 9.0 / v.max()
+    src = synth.offgrid_points(shape, 3, seed=11)
+    rec = synth.offgrid_points(shape, 7, seed=12)
+    prob = oracle.Problem(v, h, so, nt, dt, sponge=4, vref=4500.0, src=src, rec=rec)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal((nt, 3))
+    y = rng.standard_normal((nt, 7))
+    d = oracle.forward(prob, amp=w)["rec"]
+    fty = oracle.adjoint(prob, y)["src"]
+    lhs, rhs = float((d * y).sum()), float((w * fty).sum())
+    assert abs(lhs) > 0
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
+def test_offgrid_gradient_central_finite_difference_fp64():
+    n, nt, so = (20, 18, 22), 50, 8
+    v = synth.smooth_velocity(n, seed=1707, sigma=3.0).numpy().astype(np.float64)
+    dt = 0.8 * 0.4529 * 10.0 / v.max()
+    src = np.array([[9.6, 8.3, 6.45]])
+    rec = synth.offgrid_receiver_line(n, 9, depth=6.7)
+    w = synth.ricker(nt, dt, 60.0).astype(np.float64)[:, None]
+    mk = lambda vv: oracle.Problem(vv, [10.0] * 3, so, nt, dt, sponge=5, vref=4500.0, src=src, rec=rec)
+    vtrue = synth.blob_velocity(__import__("torch").from_numpy(v.astype(np.float32))).numpy().astype(np.float64)
+    d_obs = oracle.forward(mk(vtrue), amp=w)["rec"]
+    J, gv, _ = oracle.gradient(mk(v), w, d_obs)
+    dv = np.random.default_rng(8).standard_normal(v.shape) * 10.0
+    eps = 1e-3
+
+    def J_at(vv):
+        r = oracle.forward(mk(vv), amp=w)["rec"] - d_obs
+        return 0.5 * float((r * r).sum())
+
+    fd = (J_at(v + eps * dv) - J_at(v - eps * dv)) / (2 * eps)
+    an = float((gv * dv).sum())
+    assert abs(fd - an) <= 1e-7 * abs(an)
