@@ -128,14 +128,25 @@ typedef struct fd_time {
     double dt;   /* step in seconds, > 0 */
 } fd_time;
 
-/* Point set (sources or receivers) on grid nodes. */
+/* Point set (sources or receivers), on grid nodes (idx) or anywhere in the
+ * grid (pos).  A point at a position acts through multilinear interpolation
+ * over the 2^ndim nodes of the cell that holds it, with weights
+ * w_c = prod_a (c_a ? f_a : 1 - f_a), f_a the fractional part of the position
+ * (a position on the last node of an axis uses the cell below):
+ *   receiver:  d[n] = sum_c w_c u^{n+1}(c)
+ *   source:    u^{n+1}(c) += w_c 2 dt^2 w(n dt) / (2 m(c) + dt damp(c))
+ * (the operator P and its transpose, so the adjoint and the gradient stay
+ * exact transposes; an integer position is the same as the grid index, bit
+ * for bit).  Exactly one of idx and pos is non-NULL when n > 0. */
 typedef struct fd_points {
     int32_t n;           /* number of points, >= 0 */
     int32_t reserved;    /* must be 0 */
-    const int32_t *idx;  /* HOST, [n][ndim] grid indices (may be NULL if n == 0) */
+    const int32_t *idx;  /* HOST, [n][ndim] grid indices, or NULL */
     const float *amp;    /* DEVICE, [nt][n] time samples: source wavelet (forward),
                             injected residual (adjoint), observed data or trace
                             cotangent (gradient / vjp); unused where not listed */
+    const double *pos;   /* HOST, [n][ndim] positions in grid-index units
+                            (0 <= pos_a <= n_a - 1, finite; FD_EDOM otherwise), or NULL */
 } fd_points;
 
 /* Execution options; zero-initialised options mean "automatic". */

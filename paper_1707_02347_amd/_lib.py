@@ -67,6 +67,7 @@ class fd_points(C.Structure):
         ("reserved", C.c_int32),
         ("idx", C.POINTER(C.c_int32)),
         ("amp", C.c_void_p),
+        ("pos", C.POINTER(C.c_double)),
     ]
 
 
@@ -227,18 +228,29 @@ def make_time(nt, dt):
 
 
 class Points:
-    """fd_points with its host index array kept alive."""
+    """fd_points with its host array kept alive: integer arrays are grid
+    indices, floating-point arrays positions in grid-index units (points between
+    nodes, multilinear interpolation)."""
 
     def __init__(self, idx=None, amp=None, ndim=3):
+        self.pos = None
         if idx is None:
             self.idx = np.zeros((0, ndim), dtype=np.int32)
+        elif np.issubdtype(np.asarray(idx).dtype, np.floating):
+            self.pos = np.ascontiguousarray(np.asarray(idx, dtype=np.float64).reshape(-1, ndim))
+            self.idx = np.zeros((len(self.pos), ndim), dtype=np.int32)
         else:
             self.idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1, ndim))
         self.amp = amp
         s = fd_points()
         s.n = len(self.idx)
         s.reserved = 0
-        s.idx = self.idx.ctypes.data_as(C.POINTER(C.c_int32)) if len(self.idx) else None
+        if self.pos is not None:
+            s.idx = None
+            s.pos = self.pos.ctypes.data_as(C.POINTER(C.c_double)) if len(self.pos) else None
+        else:
+            s.idx = self.idx.ctypes.data_as(C.POINTER(C.c_int32)) if len(self.idx) else None
+            s.pos = None
         s.amp = _ptr(amp)
         self.s = s
 

@@ -287,7 +287,20 @@ constexpr int kStatBlocks = 256;
 
 struct TableBufs {
     int32_t *xptr, *xe, *yz, *id, *box;
-    float *scale;
+    float *scale, *wt;
+    // points between nodes: per point, its entries in corner order (CSR), and
+    // the recorded entry values [nt][cnt]
+    bool interp;
+    int32_t *pptr, *pent;
+    float *etr;
+};
+
+// Sizes of a point set's table: points, entries (2^ndim per point between
+// nodes, an upper bound), and whether it interpolates.
+struct PtsSpec {
+    int n = 0;
+    int ent = 0;
+    bool interp = false;
 };
 
 struct Layout {
@@ -308,31 +321,40 @@ struct Layout {
     size_t bytes = 0;
 };
 
-TableBufs carve_table(Carver &cv, int nx, int cnt)
+TableBufs carve_table(Carver &cv, int nx, const PtsSpec &p, int64_t rows)
 {
-    TableBufs t;
+    TableBufs t{};
+    const int cnt = std::max(p.ent, 1);
     t.xptr = cv.take<int32_t>(nx + 1);
-    t.xe = cv.take<int32_t>(std::max(cnt, 1));
-    t.yz = cv.take<int32_t>(std::max(cnt, 1));
-    t.id = cv.take<int32_t>(std::max(cnt, 1));
-    t.scale = cv.take<float>(std::max(cnt, 1));
+    t.xe = cv.take<int32_t>(cnt);
+    t.yz = cv.take<int32_t>(cnt);
+    t.id = cv.take<int32_t>(cnt);
+    t.scale = cv.take<float>(cnt);
+    t.wt = cv.take<float>(cnt);
     t.box = cv.take<int32_t>((size_t)nx * 4);
+    t.interp = p.interp;
+    if (p.interp) {
+        t.pptr = cv.take<int32_t>((size_t)p.n + 1);
+        t.pent = cv.take<int32_t>(cnt);
+        t.etr = cv.take<float>((size_t)std::max<int64_t>(rows, 1) * cnt);
+    }
     return t;
 }
 
 int ckpt_interval(const fd_options *o) { return (o && o->ckpt_every > 0) ? o->ckpt_every : 50; }
 
-Layout layout(void *ws, const Dims &d, int64_t nt, int ns, int nr, int op, int nfields,
-              int K)
+Layout layout(void *ws, const Dims &d, int64_t nt, const PtsSpec &S, const PtsSpec &R, int op,
+              int nfields, int K)
 {
+    const int ns = S.n, nr = R.n;
     Carver cv(ws);
     Layout L;
     L.q = cv.take<float>(d.Np);
     L.prof = cv.take<float>((size_t)d.nx + d.ny + d.nz);
     L.nfields = nfields;
     for (int i = 0; i < nfields; ++i) L.fields[i] = cv.take<float>(d.Np);
-    L.src = carve_table(cv, d.nx, ns);
-    L.rec = carve_table(cv, d.nx, nr);
+    L.src = carve_table(cv, d.nx, S, nt);
+    L.rec = carve_table(cv, d.nx, R, nt);
     L.vstat = cv.take<float>(3 * kStatBlocks);
     L.rpart = cv.take<double>(kStatBlocks);
     if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
@@ -550,18 +572,66 @@ KernelKey key_for(const KernelKey &base, int T, int mode, bool iso)
 // ------------------------------------------------------------------ point tables
 struct Entry {
     int x, y, z, id;
+    int corner;  // bit 2: +x, bit 1: +y, bit 0: +z from the cell's lowest node
+    float wt;
 };
+
+// The nodes of the cell that holds a position (ndim coordinates in grid-index
+// units) with their multilinear weights prod_a (c_a ? f_a : 1 - f_a), nodes of
+// weight zero left out (an integer position keeps one node of weight 1); -1 if
+// a coordinate is not finite or lies outside [0, n - 1].
+int cell_of(const Dims &d, const double *pos, int id, std::vector<Entry> &out)
+{
+    static const int map[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    const int n3[3] = {d.nx, d.ny, d.nz};
+    int base[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d.ndim; ++a) {
+        const int ax = map[d.ndim][a];
+        const double x = pos[a];
+        if (!(x >= 0.0) || !(x <= (double)(n3[ax] - 1))) return -1;
+        int i = (int)std::floor(x);
+        i = std::max(0, std::min(i, n3[ax] - 2));  // the last node: the cell below, f = 1
+        base[ax] = i;
+        f[ax] = x - (double)i;
+    }
+    for (int c = 0; c < 8; ++c) {
+        double w = 1.0;
+        int node[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const int bit = (c >> (2 - ax)) & 1;
+            node[ax] = base[ax] + bit;
+            w *= bit ? f[ax] : 1.0 - f[ax];
+        }
+        if (w == 0.0) continue;
+        out.push_back(Entry{node[0], node[1], node[2], id, c, (float)w});
+    }
+    return 0;
+}
+
+PtsSpec spec_of(const Dims &d, const fd_points *p)
+{
+    PtsSpec s;
+    if (!p || p->n <= 0) return s;
+    s.n = p->n;
+    s.interp = p->pos != nullptr;
+    s.ent = s.interp ? p->n * (1 << d.ndim) : p->n;
+    return s;
+}
 
 int build_table(const Dims &d, const fd_points *pts, std::vector<Entry> &ent)
 {
     ent.clear();
     if (!pts || pts->n == 0) return FD_OK;
-    if (pts->n < 0 || pts->reserved != 0 || !pts->idx) return FD_EINVAL;
-    ent.resize(pts->n);
+    if (pts->n < 0 || pts->reserved != 0 || (!pts->idx == !pts->pos)) return FD_EINVAL;
     for (int i = 0; i < pts->n; ++i) {
+        if (pts->pos) {
+            if (cell_of(d, pts->pos + (size_t)i * d.ndim, i, ent) < 0) return FD_EDOM;
+            continue;
+        }
         int x, y, z;
         if (node_of(d, pts->idx + (size_t)i * d.ndim, x, y, z) < 0) return FD_EDOM;
-        ent[i] = Entry{x, y, z, i};
+        ent.push_back(Entry{x, y, z, i, 0, 1.0f});
     }
     std::stable_sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) {
         if (a.x != b.x) return a.x < b.x;
@@ -572,12 +642,19 @@ int build_table(const Dims &d, const fd_points *pts, std::vector<Entry> &ent)
     return FD_OK;
 }
 
+int check_position(const Dims &d, const double *pos)
+{
+    std::vector<Entry> tmp;
+    return cell_of(d, pos, 0, tmp);
+}
+
 // Host staging of a table; kept alive until the copies are enqueued (pageable
 // copies are staged by the runtime before hipMemcpyAsync returns).
-void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs &b,
+void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs &b, int npts,
                   hipStream_t s)
 {
     std::vector<int32_t> xptr(d.nx + 1, 0), xe(ent.size()), yz(ent.size()), id(ent.size());
+    std::vector<float> wt(ent.size());
     // per-plane bounding box of the entries, so that a tile skips the planes
     // whose points it cannot hold without reading their entries
     std::vector<int32_t> box((size_t)d.nx * 4);
@@ -592,6 +669,7 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
         xe[j] = e.x;
         yz[j] = e.y * d.nzp + e.z;
         id[j] = e.id;
+        wt[j] = e.wt;
         int32_t *bx = &box[4 * (size_t)e.x];
         if (!seen[e.x]) {
             bx[0] = bx[1] = e.y;
@@ -611,6 +689,23 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
         FDW_HIP(hipMemcpyAsync(b.yz, yz.data(), yz.size() * 4, hipMemcpyHostToDevice, s));
         FDW_HIP(hipMemcpyAsync(b.id, id.data(), id.size() * 4, hipMemcpyHostToDevice, s));
         FDW_HIP(hipMemcpyAsync(b.box, box.data(), box.size() * 4, hipMemcpyHostToDevice, s));
+        FDW_HIP(hipMemcpyAsync(b.wt, wt.data(), wt.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    std::vector<int32_t> pptr, pent;
+    if (b.interp && npts > 0) {
+        // entries of each point, in corner order: the order of the sums that
+        // turn recorded entry values into traces
+        std::vector<std::vector<std::pair<int, int>>> per(npts);
+        for (size_t j = 0; j < ent.size(); ++j) per[ent[j].id].push_back({ent[j].corner, (int)j});
+        pptr.assign(npts + 1, 0);
+        for (int p = 0; p < npts; ++p) {
+            std::sort(per[p].begin(), per[p].end());
+            pptr[p + 1] = pptr[p] + (int)per[p].size();
+            for (auto &cj : per[p]) pent.push_back(cj.second);
+        }
+        FDW_HIP(hipMemcpyAsync(b.pptr, pptr.data(), pptr.size() * 4, hipMemcpyHostToDevice, s));
+        if (!pent.empty())
+            FDW_HIP(hipMemcpyAsync(b.pent, pent.data(), pent.size() * 4, hipMemcpyHostToDevice, s));
     }
     FDW_HIP(hipStreamSynchronize(s));
 }
@@ -623,6 +718,8 @@ PointTable as_table(const TableBufs &b, int stride, int cnt, bool with_scale)
     t.yz = b.yz;
     t.id = b.id;
     t.scale = with_scale ? b.scale : nullptr;
+    t.wt = b.wt;
+    t.etr = b.interp ? b.etr : nullptr;
     t.box = b.box;
     t.stride = stride;
     t.cnt = cnt;
@@ -703,9 +800,14 @@ int check_points(const Dims &d, const fd_points *p, bool need_amp, int64_t nt)
 {
     if (!p) return FD_OK;
     if (p->n < 0 || p->reserved != 0) return FD_EINVAL;
-    if (p->n > 0 && !p->idx) return FD_EINVAL;
+    if (p->n > 0 && !p->idx == !p->pos) return FD_EINVAL;  // exactly one of idx, pos
+    if (p->n > (1 << 24)) return FD_EINVAL;
     if (need_amp && p->n > 0 && nt > 0 && !p->amp) return FD_EINVAL;
     for (int i = 0; i < p->n; ++i) {
+        if (p->pos) {
+            if (check_position(d, p->pos + (size_t)i * d.ndim) < 0) return FD_EDOM;
+            continue;
+        }
         int x, y, z;
         if (node_of(d, p->idx + (size_t)i * d.ndim, x, y, z) < 0) return FD_EDOM;
     }
@@ -749,8 +851,8 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     if (rc) return rc;
     rc = build_table(d, rec, er);
     if (rc) return rc;
-    upload_table(d, es, c.L.src, c.s);
-    upload_table(d, er, c.L.rec, c.s);
+    upload_table(d, es, c.L.src, inj ? inj->n : 0, c.s);
+    upload_table(d, er, c.L.rec, rec ? rec->n : 0, c.s);
 
     SweepArgs &a = c.base;
     std::memset(&a, 0, sizeof a);
@@ -966,6 +1068,20 @@ int ws_check(void *ws, size_t ws_bytes, size_t need)
     return FD_OK;
 }
 
+// Points between nodes record one value per (point, node) entry during the
+// sweep; this turns the nt recorded rows into traces: out[row][p] = rscale *
+// sum_c w_c e[row][c] over the point's nodes in corner order.
+void gather_traces(Ctx &c, const TableBufs &b, int npts, int cnt, float *out, float rscale)
+{
+    if (!b.interp || npts <= 0 || c.nt <= 0 || !out) return;
+    const float *etr = b.etr, *wt = b.wt;
+    const int32_t *pptr = b.pptr, *pent = b.pent;
+    const int64_t rows = c.nt;
+    c.ex.call([=](hipStream_t s) {
+        return launch_gather(etr, rows, cnt, pptr, pent, wt, npts, out, rscale, s);
+    });
+}
+
 }  // namespace
 
 // fd_forward in two phases: setup (eager) and issue (through c.ex).
@@ -992,10 +1108,10 @@ int fwd_setup(FwdJob &j, const fd_grid *grid, const fd_time *time, const float *
     c.s = (hipStream_t)stream;
     c.ex.s = c.s;
     if ((rc = make_plan(c.d, opts, c.plan))) return rc;
-    const int ns = src ? src->n : 0;
-    c.L = layout(nullptr, c.d, c.nt, ns, j.nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+    const PtsSpec S = spec_of(c.d, src), R = spec_of(c.d, rec);
+    c.L = layout(nullptr, c.d, c.nt, S, R, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
     if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
-    c.L = layout(workspace, c.d, c.nt, ns, j.nr, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+    c.L = layout(workspace, c.d, c.nt, S, R, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
     j.flags = opts ? opts->flags : 0u;
     if ((rc = prepare(c, grid, v, src, 1.0f, rec, j.flags))) return rc;
     c.base.amp = src ? src->amp : nullptr;
@@ -1041,6 +1157,7 @@ void fwd_issue(FwdJob &j)
     st.spare[2] = nullptr;
     st.nspare = 2;
     advance(c, st, 0, c.nt, StepOpts{});
+    gather_traces(c, c.L.rec, j.nr, c.base.rec.cnt, c.base.rec_out, 1.0f);
     if (j.u_state && !direct) {
         float *U = j.u_state;
         const float *cur = st.cur, *prev = st.prev;
@@ -1103,9 +1220,10 @@ size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_poin
     Dims d;
     if (make_dims(grid, d) || !time || time->nt < 0) return 0;
     if (op < FD_OP_FORWARD || op > FD_OP_VJP) return 0;
-    const int ns = src ? std::max(src->n, 0) : 0;
-    const int nr = rec ? std::max(rec->n, 0) : 0;
-    Layout L = layout(nullptr, d, time->nt, ns, nr, op, fields_needed(op), ckpt_interval(opts));
+    // the tables of both point sets are laid out alike, so the order (which
+    // set injects) does not change the size
+    Layout L = layout(nullptr, d, time->nt, spec_of(d, src), spec_of(d, rec), op, fields_needed(op),
+                      ckpt_interval(opts));
     return L.bytes;
 }
 
@@ -1142,9 +1260,10 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
         c.s = (hipStream_t)stream;
         c.ex.s = c.s;
         if ((rc = make_plan(c.d, opts, c.plan))) return rc;
-        c.L = layout(nullptr, c.d, c.nt, nr, ns, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
+        const PtsSpec S = spec_of(c.d, src), R = spec_of(c.d, rec);
+        c.L = layout(nullptr, c.d, c.nt, R, S, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
         if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
-        c.L = layout(workspace, c.d, c.nt, nr, ns, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
+        c.L = layout(workspace, c.d, c.nt, R, S, FD_OP_ADJOINT, fields_needed(FD_OP_ADJOINT), 1);
         const uint32_t flags = opts ? opts->flags : 0u;
         // receivers inject (scale 1 / (2m + dt damp) = q / (2 dt^2 (1 + eta))), sources record
         const float alpha = (float)(1.0 / (2.0 * c.dt * c.dt));
@@ -1166,6 +1285,7 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
         st.spare[2] = nullptr;
         st.nspare = 2;
         advance(c, st, 0, c.nt, StepOpts{});
+        gather_traces(c, c.L.rec, ns, c.base.rec.cnt, src_out, c.base.rscale);
         if (lam_state) {
             const int64_t rows = (int64_t)c.d.nx * c.d.ny;
             FDW_HIP(launch_repitch(lam_state, c.d.nz, st.cur, c.d.nzp, rows, c.d.nz, c.s));
@@ -1216,9 +1336,10 @@ int grad_setup(GradJob &j, const fd_grid *grid, const fd_time *time, const float
     if ((rc = make_plan(c.d, opts, c.plan))) return rc;
     j.K = ckpt_interval(opts);
     if (j.K < 1) return FD_EINVAL;
-    c.L = layout(nullptr, c.d, c.nt, j.ns, j.nr, op, fields_needed(op), j.K);
+    const PtsSpec S = spec_of(c.d, src), R = spec_of(c.d, rec);
+    c.L = layout(nullptr, c.d, c.nt, S, R, op, fields_needed(op), j.K);
     if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
-    c.L = layout(workspace, c.d, c.nt, j.ns, j.nr, op, fields_needed(op), j.K);
+    c.L = layout(workspace, c.d, c.nt, S, R, op, fields_needed(op), j.K);
     const uint32_t flags = opts ? opts->flags : 0u;
     if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
     // adjoint injection scale at the receivers: 1 / (2m + dt damp) = q / (2 dt^2 (1 + eta))
@@ -1260,6 +1381,7 @@ void grad_issue(GradJob &j)
         });
         advance(c, st, k0, k1 - k0, StepOpts{});
     }
+    gather_traces(c, c.L.rec, nr, c.base.rec.cnt, c.L.traces, 1.0f);
     // ---- residual (least squares) or the given cotangent
     const float *adj_src = j.y;
     if (!j.y) {
@@ -1463,7 +1585,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         if (tt.nt < 1) tt.nt = 8;
         fd_options fixed = *inout;
         hipStream_t s = (hipStream_t)stream;
-        Layout L0 = layout(nullptr, d, tt.nt, 0, 0, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        Layout L0 = layout(nullptr, d, tt.nt, PtsSpec{}, PtsSpec{}, FD_OP_FORWARD,
+                           fields_needed(FD_OP_FORWARD), 1);
         if ((rc = ws_check(workspace, ws_bytes, L0.bytes))) return rc;
         Ctx c;
         c.d = d;
@@ -1471,7 +1594,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         c.dt = tt.dt;
         c.s = s;
         c.ex.s = s;
-        c.L = layout(workspace, d, tt.nt, 0, 0, FD_OP_FORWARD, fields_needed(FD_OP_FORWARD), 1);
+        c.L = layout(workspace, d, tt.nt, PtsSpec{}, PtsSpec{}, FD_OP_FORWARD,
+                     fields_needed(FD_OP_FORWARD), 1);
         // a constant medium at 60 % of the stability limit: kernel time does not
         // depend on the values, only on the sponge branch, which is kept
         double inv_h2 = 0.0;
@@ -1488,8 +1612,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
                        prof.data() + d.nx + d.ny);
         FDW_HIP(hipMemcpyAsync(c.L.prof, prof.data(), prof.size() * 4, hipMemcpyHostToDevice, s));
         std::vector<Entry> none;
-        upload_table(d, none, c.L.src, s);
-        upload_table(d, none, c.L.rec, s);
+        upload_table(d, none, c.L.src, 0, s);
+        upload_table(d, none, c.L.rec, 0, s);
         SweepArgs &a = c.base;
         std::memset(&a, 0, sizeof a);
         a.nx = d.nx;

@@ -34,6 +34,10 @@ struct PointTable {
     const int32_t *yz;    // [cnt] y * nz + z
     const int32_t *id;    // [cnt] original point index (column of amp / record arrays)
     const float *scale;   // [cnt] injection scale (sources only), else nullptr
+    const float *wt;      // [cnt] interpolation weight of each entry (1 on grid nodes)
+    float *etr;           // recording of points between nodes: [rows][cnt], the value
+                          // at every entry, summed per point after the sweep; nullptr:
+                          // one entry per point, written straight to the trace
     const int32_t *box;   // [nx][4] bounding box of each plane's entries: min y, max y,
                           // min z, max z (empty plane: min > max)
     int32_t stride;       // number of original points (row length of amp / record)
@@ -119,6 +123,12 @@ struct KernelKey {
 // tiles of `a`; otherwise it walks the `total` tiles of the nlist entries
 // with `grid` workgroups, persistently if grid < total (iso selects the Laplacian form).
 bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
+// Traces of points between nodes from their recorded entry values:
+// out[row][p] = rscale * sum over the entries k of point p (pptr/pent, corner
+// order) of wt[k] * etr[row][k].
+hipError_t launch_gather(const float *etr, int64_t rows, int cnt, const int32_t *pptr,
+                         const int32_t *pent, const float *wt, int npts, float *out, float rscale,
+                         hipStream_t s);
 bool launch_stream_grouped(const KernelKey &key, bool iso, bool ntl, const GroupEntry *list,
                            int nlist, int total, int grid, hipStream_t s);
 // Resident workgroups per CU of a configuration's single-pass or grouped kernel

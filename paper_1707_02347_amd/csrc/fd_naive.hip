@@ -101,7 +101,31 @@ __global__ void k_record(PointTable t, int64_t sxy, const float *field, float *o
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= t.cnt) return;
     const int64_t p = (int64_t)xe[j] * sxy + t.yz[j];
-    out[row * t.stride + t.id[j]] = field[p] * rscale;
+    if (t.etr) t.etr[row * t.cnt + j] = field[p];  // summed per point after the sweep
+    else out[row * t.stride + t.id[j]] = field[p] * rscale;
+}
+
+__global__ void k_gather(const float *etr, int64_t rows, int cnt, const int32_t *pptr,
+                         const int32_t *pent, const float *wt, int npts, float *out, float rscale)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= rows * npts) return;
+    const int64_t row = i / npts;
+    const int p = (int)(i - row * npts);
+    float acc = 0.0f;
+    for (int k = pptr[p]; k < pptr[p + 1]; ++k) acc = fmaf(wt[pent[k]], etr[row * cnt + pent[k]], acc);
+    out[i] = acc * rscale;
+}
+
+hipError_t launch_gather(const float *etr, int64_t rows, int cnt, const int32_t *pptr,
+                         const int32_t *pent, const float *wt, int npts, float *out, float rscale,
+                         hipStream_t s)
+{
+    const int64_t n = rows * npts;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, etr, rows, cnt,
+                       pptr, pent, wt, npts, out, rscale);
+    return hipGetLastError();
 }
 
 // The x coordinate of every entry is recovered from the CSR row pointers.
@@ -250,7 +274,8 @@ hipError_t launch_vstats(const float *v, int64_t n, float *partial, int nb, hipS
     return hipGetLastError();
 }
 
-// Injection scale alpha * q / (1 + eta) at each entry's node (same eta as the update).
+// Injection scale alpha * w * q / (1 + eta) at each entry's node (w its interpolation
+// weight, 1 on grid nodes; same eta as the update).
 __global__ void k_scales(SweepArgs a, PointTable t, float *scale, float alpha)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,7 +285,7 @@ __global__ void k_scales(SweepArgs a, PointTable t, float *scale, float alpha)
     const int z = t.yz[j] - y * a.nzp;
     const float qv = a.q[(int64_t)x * a.sxy + t.yz[j]];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
-    scale[j] = alpha * damped(qv, eta);
+    scale[j] = (alpha * t.wt[j]) * damped(qv, eta);
 }
 
 hipError_t launch_scales(const SweepArgs &a, const PointTable &t, float *scale, float alpha,

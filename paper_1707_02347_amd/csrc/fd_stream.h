@@ -578,12 +578,25 @@ struct StreamKernel {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.rxb[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.rxe[tj]);
                 if (jb < je) {
-                    float *orow = a.rec_out + (a.rbase + (int64_t)a.rdir * step) * a.rec.stride;
-                    for (int j = jb; j < je; ++j) {
-                        const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
+                    const int64_t row = a.rbase + (int64_t)a.rdir * step;
+                    if (a.rec.etr) {
+                        // points between nodes: the value at every entry, summed
+                        // per point after the sweep
+                        float *erow = a.rec.etr + row * a.rec.cnt;
+                        for (int j = jb; j < je; ++j) {
+                            const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
 #pragma unroll
-                        for (int r = 0; r < PY; ++r)
-                            if (th.core[r] && th.bo[r] == p) orow[a.rec.id[j]] = out[r] * a.rscale;
+                            for (int r = 0; r < PY; ++r)
+                                if (th.core[r] && th.bo[r] == p) erow[j] = out[r];
+                        }
+                    } else {
+                        float *orow = a.rec_out + row * a.rec.stride;
+                        for (int j = jb; j < je; ++j) {
+                            const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
+#pragma unroll
+                            for (int r = 0; r < PY; ++r)
+                                if (th.core[r] && th.bo[r] == p) orow[a.rec.id[j]] = out[r] * a.rscale;
+                        }
                     }
                 }
             }

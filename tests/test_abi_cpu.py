@@ -149,6 +149,32 @@ def test_unsupported_tile_is_reported():
     assert _call_forward(g, t, ws=C.c_void_p(0x10000), ws_bytes=need, opts=o) == L.FD_EINVAL
 
 
+def test_offgrid_points_validate_on_host():
+    g, t = _grid(), L.make_time(10, 1e-3)
+    # positions: finite and within [0, n - 1] on every axis, else FD_EDOM
+    for bad in ([[-0.01, 1.0, 1.0]], [[1.0, 1.0, float("nan")]], [[1.0, 1.0, 99.5]]):
+        rec = L.Points(np.array(bad, dtype=np.float64), None, 3)
+        assert _call_forward(g, t, rec=rec, ws=C.c_void_p(0x10000), ws_bytes=1 << 40) == L.FD_EDOM
+    # exactly one of idx and pos
+    rec = L.Points(np.array([[1.5, 2.0, 3.25]]), None, 3)
+    rec.s.idx = L.Points(np.array([[1, 2, 3]]), None, 3).idx.ctypes.data_as(C.POINTER(C.c_int32))
+    assert _call_forward(g, t, rec=rec, ws=C.c_void_p(0x10000), ws_bytes=1 << 40) == L.FD_EINVAL
+    rec.s.idx = None
+    rec.s.pos = None
+    assert _call_forward(g, t, rec=rec, ws=C.c_void_p(0x10000), ws_bytes=1 << 40) == L.FD_EINVAL
+
+
+def test_offgrid_points_grow_the_workspace():
+    g, t = _grid(), L.make_time(100, 1e-3)
+    on = L.Points(np.array([[1, 2, 3], [2, 2, 2]]), None, 3)
+    off = L.Points(np.array([[1.5, 2.0, 3.25], [2.0, 2.5, 2.5]]), None, 3)
+    for op in (L.FD_OP_FORWARD, L.FD_OP_ADJOINT, L.FD_OP_GRADIENT):
+        a = L.fd_workspace_size(C.byref(g), C.byref(t), C.byref(on.s), C.byref(on.s), None, op)
+        b = L.fd_workspace_size(C.byref(g), C.byref(t), C.byref(off.s), C.byref(off.s), None, op)
+        # 8 entries per point, and one recorded value per entry and step
+        assert b >= a + 2 * 100 * 8 * 4
+
+
 def test_gradient_and_adjoint_validate_on_host():
     g, t = _grid(), L.make_time(10, 1e-3)
     src = L.Points(np.array([[1, 2, 3]]), None, 3)

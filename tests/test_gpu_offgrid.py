@@ -1,0 +1,145 @@
+"""Sources and receivers between grid nodes (multilinear interpolation) on the
+GPU: forward, adjoint and gradient against the FP64 oracle (rel-L2 1e-5), every
+kernel configuration bit-identical to the untiled one, integer positions bit-
+identical to grid indices, the FP32 dot test, and batched shots equal to single
+calls."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1707_02347_amd import _lib as L
+from paper_1707_02347_amd import api
+from tests.test_gpu_parity import GRAD_TOL, make_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def offgrid_case(shape=(46, 41, 70), so=8, nt=90, sponge=6, nsrc=2, nrec=11, seed=5):
+    cs = make_case(shape, so, nt, sponge, nsrc=nsrc, nrec=nrec)
+    nd = len(shape)
+    cs["src"] = synth.offgrid_points(shape, nsrc, seed=seed, margin=1.0)
+    rec = synth.offgrid_points(shape, nrec - 3, seed=seed + 1)
+    # edge cases: the last node of every axis, the origin, and a face
+    last = np.array([[n - 1.0 for n in shape]])
+    face = np.array([[0.0] + [n / 2.0 + 0.3 for n in shape[1:]]])
+    cs["rec"] = np.concatenate([rec, last, np.zeros((1, nd)), face], 0)
+    return cs
+
+
+def gpu_fwd(cs, **opts):
+    return api.forward(cs["v"].to(DEV), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"],
+                       torch.from_numpy(cs["amp"]).to(DEV), cs["rec"], sponge=cs["sponge"], vref=cs["vref"],
+                       **opts)
+
+
+def problem(cs, v=None):
+    vv = cs["v"] if v is None else v
+    return oracle.Problem(vv.numpy().astype(np.float64), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["sponge"],
+                          cs["vref"], cs["src"], cs["rec"])
+
+
+CONFIGS = [dict(variant=L.FD_VARIANT_NAIVE), dict(variant=L.FD_VARIANT_STREAM),
+           dict(variant=L.FD_VARIANT_STREAM, tile=(7, 16, 4)),
+           dict(variant=L.FD_VARIANT_TBLOCK, tblock=2, tile=(0, 32, 4))]
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_offgrid_forward_matches_oracle_and_configs_agree(so):
+    cs = offgrid_case(so=so)
+    ref = oracle.forward(problem(cs), amp=cs["amp"].astype(np.float64))
+    outs = [gpu_fwd(cs, **o) for o in CONFIGS]
+    for o, out in zip(CONFIGS, outs):
+        er = rel_l2(out["rec"].cpu().numpy(), ref["rec"])
+        eu = rel_l2(out["u"].cpu().numpy(), ref["u"])
+        print(f"so{so} {o}: traces {er:.2e} field {eu:.2e}")
+        assert er <= 1e-5 and eu <= 1e-5
+    for out in outs[1:]:
+        assert torch.equal(out["rec"], outs[0]["rec"])
+        assert torch.equal(out["u"], outs[0]["u"])
+
+
+def test_offgrid_2d_forward_matches_oracle():
+    cs = offgrid_case(shape=(120, 96), so=4, nt=120, nsrc=1, nrec=9)
+    ref = oracle.forward(problem(cs), amp=cs["amp"].astype(np.float64))
+    out = gpu_fwd(cs)
+    assert rel_l2(out["rec"].cpu().numpy(), ref["rec"]) <= 1e-5
+    assert rel_l2(out["u"].cpu().numpy(), ref["u"]) <= 1e-5
+
+
+def test_integer_positions_equal_grid_indices_bitwise():
+    cs = make_case((40, 42, 66), 8, 60, 5, nsrc=2, nrec=6)
+    pos = dict(cs, src=cs["src"].astype(np.float64), rec=cs["rec"].astype(np.float64))
+    for o in CONFIGS[:2]:
+        a, b = gpu_fwd(cs, **o), gpu_fwd(pos, **o)
+        assert torch.equal(a["rec"], b["rec"]) and torch.equal(a["u"], b["u"])
+
+
+def test_offgrid_adjoint_matches_oracle_and_dot_test():
+    cs = offgrid_case(nt=80)
+    y = np.random.default_rng(9).standard_normal((cs["nt"], len(cs["rec"]))).astype(np.float32)
+    ref = oracle.adjoint(problem(cs), y.astype(np.float64))["src"]
+    outs = []
+    for o in CONFIGS:
+        fty = api.adjoint(cs["v"].to(DEV), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["rec"],
+                          torch.from_numpy(y).to(DEV), sponge=cs["sponge"], vref=cs["vref"], **o)["src"]
+        e = rel_l2(fty.cpu().numpy(), ref)
+        print(f"adjoint {o}: {e:.2e}")
+        assert e <= 1e-5
+        outs.append(fty)
+    for f in outs[1:]:
+        assert torch.equal(f, outs[0])
+    d = gpu_fwd(cs)["rec"].cpu().numpy().astype(np.float64)
+    lhs = float((d * y).sum())
+    rhs = float((cs["amp"].astype(np.float64) * outs[0].cpu().numpy().astype(np.float64)).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_offgrid_gradient_matches_oracle_and_configs_agree():
+    cs = make_case((40, 36, 44), 4, 120, 6, f0=25.0, nsrc=1, nrec=12)
+    cs["src"] = np.array([[19.4, 17.7, 14.35]])
+    cs["rec"] = synth.offgrid_receiver_line(cs["shape"], 12, depth=14.6)
+    vtrue = synth.blob_velocity(cs["v"], amp=0.05, width_frac=1 / 8)
+    d_obs = oracle.forward(problem(cs, vtrue), amp=cs["amp"].astype(np.float64))["rec"].astype(np.float32)
+    Jref, gref, _ = oracle.gradient(problem(cs), cs["amp"].astype(np.float64), d_obs.astype(np.float64))
+    args = (cs["v"].to(DEV), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], torch.from_numpy(cs["amp"]).to(DEV),
+            cs["rec"], torch.from_numpy(d_obs).to(DEV))
+    kw = dict(sponge=cs["sponge"], vref=cs["vref"])
+    J0, g0, _ = api.gradient(*args, variant=L.FD_VARIANT_NAIVE, ckpt_every=16, **kw)
+    eg = rel_l2(g0.cpu().numpy(), gref)
+    print(f"off-grid gradient: J {J0:.9e} vs {Jref:.9e}; rel_l2 {eg:.2e}")
+    assert abs(J0 - Jref) <= 1e-4 * Jref
+    assert eg <= GRAD_TOL
+    for o in (dict(variant=L.FD_VARIANT_STREAM, ckpt_every=16), dict(variant=L.FD_VARIANT_STREAM, ckpt_every=7),
+              dict(variant=L.FD_VARIANT_TBLOCK, tblock=2, ckpt_every=25)):
+        J, g, _ = api.gradient(*args, **o, **kw)
+        assert J == J0
+        assert torch.equal(g, g0), o
+
+
+def test_offgrid_batch_equals_single_shots():
+    shots = []
+    for i, (shape, so, nt) in enumerate([((40, 38, 44), 4, 30), ((36, 44, 52), 8, 25), ((48, 40, 46), 16, 20)]):
+        v = synth.smooth_velocity(shape, seed=400 + i, sigma=3.0).to(DEV)
+        dt = 0.8 * 2.0 / (float(v.max()) * np.sqrt(3 * 7.5)) * 10.0
+        amp = torch.from_numpy(synth.ricker(nt, dt, 30.0)[:, None].copy()).to(DEV)
+        src = synth.offgrid_points(shape, 1, seed=40 + i, margin=2.0)
+        rec = synth.offgrid_receiver_line(shape, 9, depth=12.4)
+        shots.append(dict(v=v, h=[10.0] * 3, so=so, nt=nt, dt=dt, src_idx=src, src_amp=amp, rec_idx=rec,
+                          sponge=4, vref=4500.0, options={}))
+    outs = api.forward_batch(shots, graph=True)
+    for sh, o in zip(shots, outs):
+        ref = api.forward(sh["v"], sh["h"], sh["so"], sh["nt"], sh["dt"], sh["src_idx"], sh["src_amp"], sh["rec_idx"],
+                          sponge=4, vref=4500.0)["rec"]
+        assert torch.equal(o, ref)
+    for sh in shots:
+        sh["d_obs"] = api.forward(sh["v"] * 1.02, sh["h"], sh["so"], sh["nt"], sh["dt"], sh["src_idx"],
+                                  sh["src_amp"], sh["rec_idx"], sponge=4, vref=4500.0)["rec"]
+        sh["options"] = dict(ckpt_every=9)
+    misfits, grads = api.gradient_batch(shots, graph=True)
+    for sh, J, g in zip(shots, misfits, grads):
+        Jr, gr, _ = api.gradient(sh["v"], sh["h"], sh["so"], sh["nt"], sh["dt"], sh["src_idx"], sh["src_amp"],
+                                 sh["rec_idx"], sh["d_obs"], sponge=4, vref=4500.0, ckpt_every=9)
+        assert J == Jr and torch.equal(g, gr)
