@@ -273,7 +273,33 @@ def time_blocking_study(nt=48):
     return out
 
 
-def gradient_rate(reps=2, warmup=1):
+def offgrid(cs):
+    """The same workload with its source and receivers moved between grid nodes
+    (multilinear interpolation): source +0.37 / -0.39 / +0.45 cells off its node,
+    receivers on a line at fractional x, y + 0.29 and depth 20.37."""
+    import synth
+
+    out = dict(cs)
+    out["src"] = cs["src"].astype(np.float64) + np.array([[0.37, -0.39, 0.45]])
+    nrec = 256 if cs["rec"] is None else len(cs["rec"])
+    out["rec"] = synth.offgrid_receiver_line(cs["v"].shape, nrec, depth=20.37)
+    return out
+
+
+def offgrid_rates(cs):
+    """cfg2 sweep with 256 receivers, on grid nodes and between them (GPts/s)."""
+    import synth
+
+    on = dict(cs, rec=synth.receiver_line(cs["v"].shape, 256, depth=20))
+    npts = int(np.prod(cs["v"].shape))
+    out = {}
+    for name, c in (("on_grid_256rec", on), ("off_grid_256rec", offgrid(on))):
+        med, _, _ = time_sweeps(c, launch_options("cfg2"), 3, 1)
+        out[name] = round(npts * c["nt"] / ((med - setup_ms(c, launch_options("cfg2"))) * 1e-3) / 1e9, 2)
+    return out
+
+
+def gradient_rate(reps=2, warmup=1, off_grid=False):
     """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
     import torch
 
@@ -281,6 +307,8 @@ def gradient_rate(reps=2, warmup=1):
     from paper_1707_02347_amd import api
 
     cs = workload("cfg4")
+    if off_grid:
+        cs = offgrid(cs)
     vtrue = synth.blob_velocity(cs["v"], amp=0.05, width_frac=1.0 / 16.0)
     d_obs = api.forward(vtrue, cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
                         sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg4"))["rec"]
@@ -461,6 +489,11 @@ def main():
         line["time_blocking_512cube_gpts"] = time_blocking_study()
         print("# cfg4", file=sys.stderr, flush=True)
         line["cfg4_fwi_gradient"] = gradient_rate()
+        print("# off-grid points", file=sys.stderr, flush=True)
+        og = offgrid_rates(cs)
+        g = gradient_rate(off_grid=True)
+        og["cfg4_off_grid_gradients_per_s"] = g["gradients_per_s"]
+        line["off_grid_points"] = og
         print("# cfg5", file=sys.stderr, flush=True)
         try:
             line["cfg5_batched"] = batch_rates()

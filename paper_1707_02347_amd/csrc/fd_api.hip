@@ -40,11 +40,11 @@ bool launch_stream(const KernelKey &k, const SweepArgs &a, hipStream_t s)
     return e && e->launch(a, s);
 }
 
-bool launch_stream_grouped(const KernelKey &k, bool iso, bool ntl, const GroupEntry *list,
-                           int nlist, int total, int grid, hipStream_t s)
+bool launch_stream_grouped(const KernelKey &k, bool iso, bool ntl, bool ps,
+                           const GroupEntry *list, int nlist, int total, int grid, hipStream_t s)
 {
     const StreamEntry *e = find_entry(k);
-    return e && e->launch_group(iso, ntl, list, nlist, total, grid, s);
+    return e && e->launch_group(iso, ntl, ps, list, nlist, total, grid, s);
 }
 
 // Bytes a pass re-reads every step: u^n, u^{n-1} and q, plus the FP64 image in
@@ -651,7 +651,7 @@ int check_position(const Dims &d, const double *pos)
 // Host staging of a table; kept alive until the copies are enqueued (pageable
 // copies are staged by the runtime before hipMemcpyAsync returns).
 void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs &b, int npts,
-                  hipStream_t s)
+                  std::vector<int32_t> *host_xptr, hipStream_t s)
 {
     std::vector<int32_t> xptr(d.nx + 1, 0), xe(ent.size()), yz(ent.size()), id(ent.size());
     std::vector<float> wt(ent.size());
@@ -683,6 +683,7 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
         }
     }
     for (int x = 0; x < d.nx; ++x) xptr[x + 1] += xptr[x];
+    if (host_xptr) *host_xptr = xptr;
     FDW_HIP(hipMemcpyAsync(b.xptr, xptr.data(), xptr.size() * 4, hipMemcpyHostToDevice, s));
     if (!ent.empty()) {
         FDW_HIP(hipMemcpyAsync(b.xe, xe.data(), xe.size() * 4, hipMemcpyHostToDevice, s));
@@ -784,7 +785,33 @@ struct Ctx {
     Plan plan;
     Layout L;
     SweepArgs base;   // common launch arguments
+    std::vector<int32_t> hxs, hxr;  // host copies of the point tables' plane pointers
 };
+
+// Whether a pass walks its point entries staged in LDS: a configuration that
+// can stage, a table large enough to be worth it, and every chunk's entries
+// (its planes, with the 2 (T - 1) M overlap planes of a time block) within
+// the capacity, since the staged form of the kernel has no other walk.
+bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
+{
+    if (!points_stageable(k.PY, k.NW)) return false;
+    if (a.inj.cnt <= kStageMin && a.rec.cnt <= kStageMin) return false;
+    const int cap = kPtsCap / k.T, H = (k.T - 1) * k.M;
+    auto fits = [&](const PointTable &t) {
+        if (t.cnt == 0) return true;
+        const std::vector<int32_t> *hx = (t.xptr == c.L.src.xptr)   ? &c.hxs
+                                         : (t.xptr == c.L.rec.xptr) ? &c.hxr
+                                                                    : nullptr;
+        if (!hx || hx->size() != (size_t)a.nx + 1) return false;
+        for (int x0 = 0; x0 < a.nx; x0 += a.lx) {
+            const int xend = std::min(x0 + a.lx, a.nx);
+            const int c0 = std::max(x0 - H, 0), c1 = std::min(xend + H, a.nx);
+            if ((*hx)[c1] - (*hx)[c0] > cap) return false;
+        }
+        return true;
+    };
+    return fits(a.inj) && fits(a.rec);
+}
 
 int validate_common(const fd_grid *g, const fd_time *t, const float *v, Dims &d)
 {
@@ -851,8 +878,8 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     if (rc) return rc;
     rc = build_table(d, rec, er);
     if (rc) return rc;
-    upload_table(d, es, c.L.src, inj ? inj->n : 0, c.s);
-    upload_table(d, er, c.L.rec, rec ? rec->n : 0, c.s);
+    upload_table(d, es, c.L.src, inj ? inj->n : 0, &c.hxs, c.s);
+    upload_table(d, er, c.L.rec, rec ? rec->n : 0, &c.hxr, c.s);
 
     SweepArgs &a = c.base;
     std::memset(&a, 0, sizeof a);
@@ -996,6 +1023,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.remap = c.plan.remap ? 1 : 0;
         a.alt = c.plan.alt ? 1 : 0;
         a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
+        a.ps = stage_points(c, k, a) ? 1 : 0;
         supertile(k, a);
         c.ex.pass(k, a, c.plan.loads);
         if (Tk == 1) swap_in(st, o1, st.cur);
@@ -1612,8 +1640,8 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
                        prof.data() + d.nx + d.ny);
         FDW_HIP(hipMemcpyAsync(c.L.prof, prof.data(), prof.size() * 4, hipMemcpyHostToDevice, s));
         std::vector<Entry> none;
-        upload_table(d, none, c.L.src, 0, s);
-        upload_table(d, none, c.L.rec, 0, s);
+        upload_table(d, none, c.L.src, 0, &c.hxs, s);
+        upload_table(d, none, c.L.rec, 0, &c.hxr, s);
         SweepArgs &a = c.base;
         std::memset(&a, 0, sizeof a);
         a.nx = d.nx;
@@ -1712,6 +1740,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
         KernelKey key;
         bool iso;
         bool ntl;
+        bool ps;
         size_t off;
         int n, total;
         int shot, idx;
@@ -1727,20 +1756,20 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
             if (r >= ops[sh].size()) continue;
             const Op &o = ops[sh][r];
             if (o.is_pass && stream_has_group(o.key, o.a.w.iso != 0)) passes.push_back({sh, r});
-            else plan.push_back(Launch{false, {}, false, false, 0, 0, 0, (int)sh, (int)r, 0});
+            else plan.push_back(Launch{false, {}, false, false, false, 0, 0, 0, (int)sh, (int)r, 0});
         }
         std::vector<bool> done(passes.size(), false);
         for (size_t p = 0; p < passes.size(); ++p) {
             if (done[p]) continue;
             const Op &lead = ops[passes[p].first][passes[p].second];
-            Launch L{true, lead.key, lead.a.w.iso != 0, false, host.size(), 0, 0, -1, -1, 0};
+            Launch L{true, lead.key, lead.a.w.iso != 0, false, lead.a.ps != 0, host.size(), 0, 0, -1, -1, 0};
             double resident = 0.0;
             for (size_t q = p; q < passes.size(); ++q) {
                 const Op &o = ops[passes[q].first][passes[q].second];
                 const KernelKey &k = o.key;
                 if (done[q] || k.M != lead.key.M || k.T != lead.key.T || k.PY != lead.key.PY ||
                     k.NW != lead.key.NW || k.mode != lead.key.mode || (o.a.w.iso != 0) != L.iso ||
-                    o.loads != lead.loads)
+                    o.loads != lead.loads || o.a.ps != lead.a.ps)
                     continue;
                 done[q] = true;
                 resident += resident_bytes(o.a, k.mode);
@@ -1771,7 +1800,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
     auto issue = [&](hipStream_t st) {
         for (const Launch &L : plan) {
             if (L.grouped) {
-                if (!launch_stream_grouped(L.key, L.iso, L.ntl, dev_entries + L.off, L.n, L.total,
+                if (!launch_stream_grouped(L.key, L.iso, L.ntl, L.ps, dev_entries + L.off, L.n, L.total,
                                            L.grid, st))
                     throw Status{FD_EUNSUPPORTED};
                 FDW_HIP(hipGetLastError());

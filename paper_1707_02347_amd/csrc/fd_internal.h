@@ -91,7 +91,17 @@ struct SweepArgs {
     // ntl != 0: u^{n-1}, q and the gradient fields are loaded non-temporally
     // (single-pass launches; a grouped launch takes the policy as an argument).
     int ntl;
+    // ps != 0: the point entries of every chunk fit in LDS and are staged there
+    // (single-pass launches; a grouped launch takes the choice as an argument).
+    int ps;
 };
+
+// Point entries x time levels a workgroup can stage in LDS, the configurations
+// that can (the others would spill registers), and the table size below which
+// the walk in memory is kept (a lone source costs it nothing).
+constexpr int kPtsCap = 512;
+constexpr int kStageMin = 32;
+constexpr bool points_stageable(int PY, int NW) { return NW < 16 && PY <= 4; }
 
 enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
 
@@ -129,8 +139,8 @@ bool launch_stream(const KernelKey &key, const SweepArgs &a, hipStream_t s);
 hipError_t launch_gather(const float *etr, int64_t rows, int cnt, const int32_t *pptr,
                          const int32_t *pent, const float *wt, int npts, float *out, float rscale,
                          hipStream_t s);
-bool launch_stream_grouped(const KernelKey &key, bool iso, bool ntl, const GroupEntry *list,
-                           int nlist, int total, int grid, hipStream_t s);
+bool launch_stream_grouped(const KernelKey &key, bool iso, bool ntl, bool ps,
+                           const GroupEntry *list, int nlist, int total, int grid, hipStream_t s);
 // Resident workgroups per CU of a configuration's single-pass or grouped kernel
 // (0 if not compiled).
 int stream_occupancy(const KernelKey &key, bool iso, bool grouped);

@@ -110,12 +110,18 @@ __device__ __forceinline__ void bstore64(__amdgpu_buffer_rsrc_t r, uint32_t byte
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)byte_off, 0, CP);
 }
 
-template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL, bool PS>
 struct StreamKernel {
     using G = Geo<M, T, PY, NW>;
     // cache policy of the loads each point needs once per step (u^{n-1}, q,
     // and the gradient fields)
     static constexpr int LP = NTL ? kStream : kKeep;
+    // PS: the chunk's point entries are staged in LDS (the host launches this
+    // form only when every chunk's entries fit); otherwise the per-plane walk
+    // reads the tables in memory.  Each form holds one walk only: both in one
+    // body cost the streaming loop 3.5 % (a larger unrolled body).
+    static constexpr bool STAGE = PS;
+    static constexpr int PC = PS ? kPtsCap / T : 1;
     // Register queues along x.  Short queues (M <= 4) rotate by renaming: the
     // x loop is unrolled by QS (the queue length 2M + 1 rounded up to a
     // multiple of NS below) and the slot of logical entry j (0 = oldest,
@@ -162,6 +168,19 @@ struct StreamKernel {
         float px[G::SPAN];
         int ixb[G::SPAN], ixe[G::SPAN];  // per plane: source entries this tile may hold
         int rxb[G::SPAN], rxe[G::SPAN];  // per plane: receiver entries its core may hold
+        // The point entries of the chunk's planes, staged when they fit (i0,
+        // r0: first staged table index, or -1: walk the table in memory).
+        // Sources: node, owning wave (-1: outside the owned region), scale and
+        // the amplitude of each of the pass's T steps.  Receivers: node, owning
+        // wave (-1: outside the output core or the chunk's own planes), trace
+        // column (or entry slot), and the T samples the pass records, written
+        // out after the loop.
+        // A node is coded (wave << 16) | (row in the wave << 8) | column.
+        int i0, r0;
+        int icode[PC];
+        float isc[PC], iamp[T][PC];
+        int rcode[PC], rdst[PC];
+        float rval[T][PC];
     };
 
     static constexpr bool IMG = (MODE == kImaging);
@@ -252,6 +271,13 @@ struct StreamKernel {
         // the bounding box of the plane's points misses this tile (its owned
         // region for sources, its output core for receivers)
         const int span = th.xend - th.x0 + 2 * (T - 1) * M;
+        // the chunk's range of each point table (issued here, so that its
+        // latency overlaps the per-plane loads below)
+        const int cf = max(th.cbase, 0), cl = min(th.cbase + span, a.nx);
+        const bool iwant = STAGE && a.inj.cnt > 0 && cf < cl;
+        const bool rwant = STAGE && a.rec.cnt > 0 && cf < cl;
+        const int ib = iwant ? a.inj.xptr[cf] : 0, ie = iwant ? a.inj.xptr[cl] : 0;
+        const int rb = rwant ? a.rec.xptr[cf] : 0, re = rwant ? a.rec.xptr[cl] : 0;
         for (int j = threadIdx.x; j < span; j += G::NT) {
             const int c = th.cbase + j;
             const bool cin = (unsigned)c < (unsigned)a.nx;
@@ -273,6 +299,42 @@ struct StreamKernel {
                     bx[3] >= z1 + G::H1 && bx[2] < z1 + G::H1 + G::TZ) {
                     sm.rxb[j] = b;
                     sm.rxe[j] = e;
+                }
+            }
+        }
+        // Stage the chunk's point entries (all planes it computes; the table is
+        // sorted by plane, so they are one contiguous range) in LDS.  The loop
+        // then touches only LDS for points: a global load or store inside it
+        // would make the next plane's wait also cover the prefetched loads (the
+        // counter is in order), draining the pipeline on every plane that holds
+        // points, and its per-entry work runs across lanes.
+        if constexpr (STAGE) {
+            const bool istg = iwant && ie - ib <= PC, rstg = rwant && re - rb <= PC;
+            if (threadIdx.x == 0) {
+                sm.i0 = istg ? ib : -1;
+                sm.r0 = rstg ? rb : -1;
+            }
+            if (istg)
+                for (int j = threadIdx.x; j < ie - ib; j += G::NT) {
+                    const int yz = a.inj.yz[ib + j];
+                    const int y = yz / a.nzp, rr = y - y1, cz = yz - y * a.nzp - z1;
+                    const bool own = rr >= 0 && rr < G::RY && cz >= 0 && cz < G::RZ;
+                    sm.icode[j] = own ? ((rr / PY) << 16) | ((rr % PY) << 8) | cz : -1;
+                    sm.isc[j] = a.inj.scale[ib + j];
+                    const int id = a.inj.id[ib + j];
+#pragma unroll
+                    for (int t = 0; t < T; ++t)
+                        sm.iamp[t][j] = a.amp[(a.abase + (int64_t)a.adir * (a.step0 + t)) * a.inj.stride + id];
+                }
+            if (rstg) {
+                const bool ent = a.rec.etr != nullptr;
+                for (int j = threadIdx.x; j < re - rb; j += G::NT) {
+                    const int yz = a.rec.yz[rb + j], x = a.rec.xe[rb + j];
+                    const int y = yz / a.nzp, rr = y - y1, cz = yz - y * a.nzp - z1;
+                    const bool core = rr >= G::H1 && rr < G::RY - G::H1 && cz >= G::H1 &&
+                                      cz < G::RZ - G::H1 && x >= th.x0 && x < th.xend;
+                    sm.rcode[j] = core ? ((rr / PY) << 16) | ((rr % PY) << 8) | cz : -1;
+                    sm.rdst[j] = ent ? rb + j : a.rec.id[rb + j];
                 }
             }
         }
@@ -316,6 +378,21 @@ struct StreamKernel {
 #pragma unroll
         for (int d = 0; d < ((NS > 1) ? NS - 1 : 1); ++d) load(a, th, pf[d], istart + d);
         for (int i0 = istart; i0 < th.iend; i0 += UNROLL) block<0>(a, sm, th, qu, acc, pf, i0, N);
+
+        // the samples the staged receivers recorded, one trace row per level
+        if (STAGE && re > rb && __builtin_amdgcn_readfirstlane(sm.r0) >= 0) {
+            __syncthreads();
+            const bool ent = a.rec.etr != nullptr;
+            for (int j = threadIdx.x; j < re - rb; j += G::NT) {
+                if (sm.rcode[j] < 0) continue;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const int64_t row = a.rbase + (int64_t)a.rdir * (a.step0 + t);
+                    float *orow = ent ? a.rec.etr + row * a.rec.cnt : a.rec_out + row * a.rec.stride;
+                    orow[sm.rdst[j]] = sm.rval[t][j];
+                }
+            }
+        }
     }
 
     // Iterations i0 + PH .. i0 + UNROLL - 1 of the x loop (one per phase).  Each
@@ -556,20 +633,51 @@ struct StreamKernel {
                 out[r] = active ? damped(num, eta) : 0.0f;
             }
             const int step = a.step0 + t - 1;
+            // point entries of this plane (table order; entries at one node
+            // are applied in that order), from LDS when the chunk's entries
+            // were staged
             {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.ixb[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.ixe[tj]);
                 if (jb < je) {
                     const float *arow = a.amp + (a.abase + (int64_t)a.adir * step) * a.inj.stride;
-                    for (int j = jb; j < je; ++j) {
-                        const uint32_t p = (uint32_t)a.inj.yz[j] * 4u;
-                        const float sc = a.inj.scale[j];
-                        const float w = arow[a.inj.id[j]];
+                    if constexpr (STAGE) {
+                        const int s0 = __builtin_amdgcn_readfirstlane(sm.i0);
+                        const int sw = __builtin_amdgcn_readfirstlane(wv);
+                        // staged: up to 64 entries at a time sit in the lanes of
+                        // one LDS read; the walk reads them back with lane reads
+                        for (int j0 = jb; j0 < je; j0 += 64) {
+                            const int n = min(64, je - j0), k = j0 + lane - s0;
+                            int code = -1;
+                            float scl = 0.0f, wl = 0.0f;
+                            if (lane < n) {
+                                code = sm.icode[k];
+                                scl = sm.isc[k];
+                                wl = sm.iamp[t - 1][k];
+                            }
+                            for (int kk = 0; kk < n; ++kk) {
+                                const int ck = __builtin_amdgcn_readlane(code, kk);
+                                if (ck < 0 || (ck >> 16) != sw) continue;
+                                const int rk = (ck >> 8) & 0xff, lk = ck & 0xff, rr = sw * PY + rk;
+                                if (rr < lo || rr >= G::RY - lo || lk < lo || lk >= G::RZ - lo) continue;
+                                const float sc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scl), kk));
+                                const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), kk));
 #pragma unroll
-                        for (int r = 0; r < PY; ++r) {
-                            const int rr = wv * PY + r;
-                            const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
-                            if (active && th.bo[r] == p) out[r] = fmaf(sc, w, out[r]);
+                                for (int r = 0; r < PY; ++r)
+                                    if (r == rk && lane == lk) out[r] = fmaf(sc, w, out[r]);
+                            }
+                        }
+                    } else {
+                        for (int j = jb; j < je; ++j) {
+                            const uint32_t p = (uint32_t)a.inj.yz[j] * 4u;
+                            const float sc = a.inj.scale[j];
+                            const float w = arow[a.inj.id[j]];
+#pragma unroll
+                            for (int r = 0; r < PY; ++r) {
+                                const int rr = wv * PY + r;
+                                const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
+                                if (active && th.bo[r] == p) out[r] = fmaf(sc, w, out[r]);
+                            }
                         }
                     }
                 }
@@ -578,24 +686,39 @@ struct StreamKernel {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.rxb[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.rxe[tj]);
                 if (jb < je) {
+                    // points between nodes record the value at every entry
+                    // (summed per point after the sweep); points on nodes
+                    // write their trace sample
                     const int64_t row = a.rbase + (int64_t)a.rdir * step;
-                    if (a.rec.etr) {
-                        // points between nodes: the value at every entry, summed
-                        // per point after the sweep
-                        float *erow = a.rec.etr + row * a.rec.cnt;
-                        for (int j = jb; j < je; ++j) {
-                            const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
+                    const bool ent = a.rec.etr != nullptr;
+                    float *orow = ent ? a.rec.etr + row * a.rec.cnt : a.rec_out + row * a.rec.stride;
+                    const float rs = ent ? 1.0f : a.rscale;
+                    if constexpr (STAGE) {
+                        const int s0 = __builtin_amdgcn_readfirstlane(sm.r0);
+                        const int sw = __builtin_amdgcn_readfirstlane(wv);
+                        // staged: lane k takes entry j0 + k and fetches the sample
+                        // from the lane that computed it (one permute per row);
+                        // the samples stay in LDS until the end of the chunk
+                        for (int j0 = jb; j0 < je; j0 += 64) {
+                            const int k = j0 + lane - s0;
+                            const int code = (lane < je - j0) ? sm.rcode[k] : -1;
+                            const int rk = (code >> 8) & 0xff, lk = code & 0xff;
+                            float v = 0.0f;
 #pragma unroll
-                            for (int r = 0; r < PY; ++r)
-                                if (th.core[r] && th.bo[r] == p) erow[j] = out[r];
+                            for (int r = 0; r < PY; ++r) {
+                                const float o = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(lk << 2, __float_as_int(out[r])));
+                                if (r == rk) v = o;
+                            }
+                            if (code >= 0 && (code >> 16) == sw) sm.rval[t - 1][k] = v * rs;
                         }
                     } else {
-                        float *orow = a.rec_out + row * a.rec.stride;
                         for (int j = jb; j < je; ++j) {
                             const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
+                            const int dst = ent ? j : a.rec.id[j];
 #pragma unroll
                             for (int r = 0; r < PY; ++r)
-                                if (th.core[r] && th.bo[r] == p) orow[a.rec.id[j]] = out[r] * a.rscale;
+                                if (th.core[r] && th.bo[r] == p) orow[dst] = out[r] * rs;
                         }
                     }
                 }
@@ -657,10 +780,10 @@ struct StreamKernel {
 
 // One pass of one shot: workgroup b runs tile b (arguments by value, so every
 // field lives in scalar registers or the kernel-argument segment).
-template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL, bool PS>
 __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 {
-    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL>;
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL, PS>;
     __shared__ typename K::Smem sm;
     K::run(a, sm, blockIdx.x, gridDim.x);
 }
@@ -671,11 +794,11 @@ __global__ __launch_bounds__(64 * NW) void k_stream(SweepArgs a)
 // grid is a multiple of 8, the items of one round are dealt so that each XCD
 // takes a contiguous block of them (neighbouring tiles of one shot share that
 // XCD's L2).
-template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL, bool PS>
 __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__restrict__ list,
                                                             int nlist, int total)
 {
-    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL>;
+    using K = StreamKernel<M, T, PY, NW, MODE, ISO, NTL, PS>;
     __shared__ typename K::Smem sm;
     const int b = blockIdx.x;
     const int first = ((gridDim.x & 7) == 0) ? (b & 7) * (gridDim.x >> 3) + (b >> 3) : b;
@@ -700,16 +823,27 @@ __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__
     }
 }
 
-// Launch helpers shared by the generated entry files.  The non-temporal-load
-// form (a.ntl, or ntl for a grouped launch) differs from the other only in
-// cache-policy bits, so both give identical results.
+// Launch helpers shared by the generated entry files.  The forms differ in the
+// cache policy of once-per-step loads (a.ntl, or ntl for a grouped launch) and
+// in the point walk (a.ps / ps: staged, for configurations that can stage);
+// all forms give identical results.
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
+void issue_stream_p(const SweepArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    if constexpr (points_stageable(PY, NW)) {
+        if (a.ps) {
+            hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, NTL, true>), grid, block, 0, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, NTL, false>), grid, block, 0, s, a);
+}
+
 template <int M, int T, int PY, int NW, int MODE, bool ISO>
 void issue_stream(const SweepArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (a.ntl)
-        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, false>), grid, block, 0, s, a);
+    if (a.ntl) issue_stream_p<M, T, PY, NW, MODE, ISO, true>(a, grid, block, s);
+    else issue_stream_p<M, T, PY, NW, MODE, ISO, false>(a, grid, block, s);
 }
 
 template <int M, int T, int PY, int NW, int MODE, int F>
@@ -727,30 +861,41 @@ bool entry_launch(const SweepArgs &a, hipStream_t s)
     return false;
 }
 
-template <int M, int T, int PY, int NW, int MODE, bool ISO>
-void issue_grouped(bool ntl, const GroupEntry *list, int nlist, int total, dim3 grid, dim3 block,
-                    hipStream_t s)
+template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
+void issue_grouped_p(bool ps, const GroupEntry *list, int nlist, int total, dim3 grid, dim3 block,
+                     hipStream_t s)
 {
-    if (ntl)
-        hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, true>), grid, block, 0, s,
-                           list, nlist, total);
-    else
-        hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, false>), grid, block, 0, s,
-                           list, nlist, total);
+    if constexpr (points_stageable(PY, NW)) {
+        if (ps) {
+            hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, NTL, true>), grid, block, 0,
+                               s, list, nlist, total);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, NTL, false>), grid, block, 0, s,
+                       list, nlist, total);
+}
+
+template <int M, int T, int PY, int NW, int MODE, bool ISO>
+void issue_grouped(bool ntl, bool ps, const GroupEntry *list, int nlist, int total, dim3 grid,
+                   dim3 block, hipStream_t s)
+{
+    if (ntl) issue_grouped_p<M, T, PY, NW, MODE, ISO, true>(ps, list, nlist, total, grid, block, s);
+    else issue_grouped_p<M, T, PY, NW, MODE, ISO, false>(ps, list, nlist, total, grid, block, s);
 }
 
 template <int M, int T, int PY, int NW, int MODE, int F>
-bool entry_launch_group(bool iso, bool ntl, const GroupEntry *list, int nlist, int total,
+bool entry_launch_group(bool iso, bool ntl, bool ps, const GroupEntry *list, int nlist, int total,
                         int grid, hipStream_t s)
 {
     if constexpr ((F & 2) != 0) {
         const dim3 g(grid), block(64 * NW);
         if (iso) {
-            issue_grouped<M, T, PY, NW, MODE, true>(ntl, list, nlist, total, g, block, s);
+            issue_grouped<M, T, PY, NW, MODE, true>(ntl, ps, list, nlist, total, g, block, s);
             return true;
         }
         if constexpr ((F & 1) != 0) {
-            issue_grouped<M, T, PY, NW, MODE, false>(ntl, list, nlist, total, g, block, s);
+            issue_grouped<M, T, PY, NW, MODE, false>(ntl, ps, list, nlist, total, g, block, s);
             return true;
         }
     }
@@ -758,8 +903,8 @@ bool entry_launch_group(bool iso, bool ntl, const GroupEntry *list, int nlist, i
 }
 
 // Resident workgroups per CU of the single-pass or the grouped kernel (0 if the
-// requested form is not compiled).  Both cache-policy forms use the same
-// registers and LDS.
+// requested form is not compiled).  All cache-policy and point-walk forms use
+// the same registers and LDS closely enough that the plain form stands for them.
 template <int M, int T, int PY, int NW, int MODE, int F>
 int entry_occupancy(bool iso, bool grouped)
 {
@@ -769,14 +914,14 @@ int entry_occupancy(bool iso, bool grouped)
     if (grouped) {
         if constexpr ((F & 2) != 0) {
             if (iso)
-                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true, false>);
+                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, true, false, false>);
             else if constexpr ((F & 1) != 0)
-                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false, false>);
+                fn = reinterpret_cast<const void *>(&k_stream_grouped<M, T, PY, NW, MODE, false, false, false>);
         }
     } else {
-        if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true, false>);
+        if (iso) fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, true, false, false>);
         else if constexpr ((F & 1) != 0)
-            fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, false, false>);
+            fn = reinterpret_cast<const void *>(&k_stream<M, T, PY, NW, MODE, false, false, false>);
     }
     if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * NW, 0);
     return e == hipSuccess ? n : 0;

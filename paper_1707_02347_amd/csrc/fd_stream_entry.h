@@ -10,7 +10,7 @@ namespace fdw {
 struct StreamEntry {
     int M, T, PY, NW, mode, flags;  // flags: bit 0 anisotropic form, bit 1 grouped kernel
     bool (*launch)(const SweepArgs &a, hipStream_t s);
-    bool (*launch_group)(bool iso, bool ntl, const GroupEntry *list, int nlist, int total,
+    bool (*launch_group)(bool iso, bool ntl, bool ps, const GroupEntry *list, int nlist, int total,
                          int grid, hipStream_t s);
     int (*occupancy)(bool iso, bool grouped);
 };

@@ -79,7 +79,7 @@ def configs_for(so, small_chunk=7):
               3: [(32, 8, 1), (32, 4, 1)],
               4: [(32, 8, 1), (16, 4, 1), (32, 16, 1), (16, 8, 1), (32, 4, 1), (32, 2, 1), (16, 2, 1),
                   (32, 4, 2), (32, 2, 2), (32, 4, 3), (32, 2, 3)],
-              8: [(32, 8, 1), (16, 4, 1), (16, 8, 1), (32, 4, 1), (32, 2, 1), (32, 4, 2), (32, 2, 2),]}.get(M, [(32, 8, 1), (16, 4, 1)])
+              8: [(32, 8, 1), (16, 4, 1), (16, 8, 1), (32, 4, 1), (32, 2, 1), (32, 4, 2)]}.get(M, [(32, 8, 1), (16, 4, 1)])
     for rows, py, tb in shapes:
         var = L.FD_VARIANT_STREAM if tb == 1 else L.FD_VARIANT_TBLOCK
         out.append(dict(variant=var, tile=(0, rows, py), tblock=tb))
