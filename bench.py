@@ -299,7 +299,7 @@ def offgrid_rates(cs):
     return out
 
 
-def gradient_rate(reps=2, warmup=1, off_grid=False):
+def gradient_rate(reps=2, warmup=1, off_grid=False, ckpt_every=50):
     """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
     import torch
 
@@ -316,7 +316,7 @@ def gradient_rate(reps=2, warmup=1, off_grid=False):
 
     def run():
         out["J"], out["g"], _ = api.gradient(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"],
-                                             cs["rec"], d_obs, sponge=cs["sponge"], vref=cs["vref"], ckpt_every=50,
+                                             cs["rec"], d_obs, sponge=cs["sponge"], vref=cs["vref"], ckpt_every=ckpt_every,
                                              **launch_options("cfg4"))
 
     med, mean, std = _timed(run, reps, warmup)
@@ -494,6 +494,9 @@ def main():
         g = gradient_rate(off_grid=True)
         og["cfg4_off_grid_gradients_per_s"] = g["gradients_per_s"]
         line["off_grid_points"] = og
+        # the whole time axis stored (1000 second differences, 64 GB) instead of
+        # checkpoints every 50 steps: no recomputation sweep
+        line["cfg4_full_storage_gradients_per_s"] = gradient_rate(ckpt_every=1000)["gradients_per_s"]
         print("# cfg5", file=sys.stderr, flush=True)
         try:
             line["cfg5_batched"] = batch_rates()

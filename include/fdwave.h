@@ -208,8 +208,10 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v,
  *   dJ/dv = dJ/dm * (-2 / v^3).
  * Forward wavefields are checkpointed every ckpt_every steps (u^{jk}, u^{jk-1}) and
  * recomputed segment by segment (the paper's buffered vs saved time dimension,
- * Sec. 6.3.2, traded through recomputation).  The imaging sum is accumulated
- * in FP64.
+ * Sec. 6.3.2, traded through recomputation).  With ckpt_every >= nt the whole
+ * time axis is stored instead (workspace about nt fields): the forward sweep
+ * saves every second difference and no recomputation runs, two sweeps instead
+ * of three; results are identical.  The imaging sum is accumulated in FP64.
  *   src->amp DEVICE [nt][ns] source wavelet; rec->amp DEVICE [nt][nr] observed data.
  *   grad_v   DEVICE [N] FP32 result.
  *   misfit   HOST double or NULL (non-NULL: the call waits for it).

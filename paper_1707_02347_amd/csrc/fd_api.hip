@@ -1399,15 +1399,28 @@ void grad_issue(GradJob &j)
             return e == hipSuccess ? launch_zero(a1, N * 4, s) : e;
         });
     }
-    for (int jck = 0; jck < c.L.nck; ++jck) {
-        const int64_t k0 = (int64_t)jck * K, k1 = std::min<int64_t>(k0 + K, c.nt);
-        float *ck = c.L.ckpt + (size_t)jck * 2 * N;
-        float *cur = st.cur, *prev = st.prev;
-        c.ex.call([ck, cur, prev, N](hipStream_t s) {
-            hipError_t e = copy_async(ck, cur, N, s);
-            return e == hipSuccess ? copy_async(ck + N, prev, N, s) : e;
-        });
-        advance(c, st, k0, k1 - k0, StepOpts{});
+    // One segment (checkpoint interval >= nt: the whole time axis is stored,
+    // the paper's "saved" time dimension): the forward sweep itself writes
+    // every second difference, and the adjoint needs no recomputation
+    // (two sweeps instead of three).
+    const bool full = c.L.nck == 1;
+    if (full) {
+        StepOpts fo;
+        fo.mode = kSaveD2;
+        fo.dslot_first = 0;  // step n produces u^{n+1}: slot n
+        fo.ddir = 1;
+        advance(c, st, 0, c.nt, fo);
+    } else {
+        for (int jck = 0; jck < c.L.nck; ++jck) {
+            const int64_t k0 = (int64_t)jck * K, k1 = std::min<int64_t>(k0 + K, c.nt);
+            float *ck = c.L.ckpt + (size_t)jck * 2 * N;
+            float *cur = st.cur, *prev = st.prev;
+            c.ex.call([ck, cur, prev, N](hipStream_t s) {
+                hipError_t e = copy_async(ck, cur, N, s);
+                return e == hipSuccess ? copy_async(ck + N, prev, N, s) : e;
+            });
+            advance(c, st, k0, k1 - k0, StepOpts{});
+        }
     }
     gather_traces(c, c.L.rec, nr, c.base.rec.cnt, c.L.traces, 1.0f);
     // ---- residual (least squares) or the given cotangent
@@ -1448,21 +1461,23 @@ void grad_issue(GradJob &j)
     const SweepArgs saved = c.base;
     for (int jck = c.L.nck - 1; jck >= 0; --jck) {
         const int64_t k0 = (int64_t)jck * K, k1 = std::min<int64_t>(k0 + K, c.nt);
-        const float *ck = c.L.ckpt + (size_t)jck * 2 * N;
-        State sf{F[0], F[1], {F[2], F[3], F[4]}, 3};
-        {
-            float *cur = sf.cur, *prev = sf.prev;
-            c.ex.call([ck, cur, prev, N](hipStream_t s) {
-                hipError_t e = copy_async(cur, ck, N, s);
-                return e == hipSuccess ? copy_async(prev, ck + N, N, s) : e;
-            });
+        if (!full) {
+            const float *ck = c.L.ckpt + (size_t)jck * 2 * N;
+            State sf{F[0], F[1], {F[2], F[3], F[4]}, 3};
+            {
+                float *cur = sf.cur, *prev = sf.prev;
+                c.ex.call([ck, cur, prev, N](hipStream_t s) {
+                    hipError_t e = copy_async(cur, ck, N, s);
+                    return e == hipSuccess ? copy_async(prev, ck + N, N, s) : e;
+                });
+            }
+            c.base = fwd;
+            StepOpts fo;
+            fo.mode = kSaveD2;
+            fo.dslot_first = 0;  // step k0 produces u^{k0+1}: slot (k0+1) - k0 - 1 = 0
+            fo.ddir = 1;
+            advance(c, sf, k0, k1 - k0, fo);
         }
-        c.base = fwd;
-        StepOpts fo;
-        fo.mode = kSaveD2;
-        fo.dslot_first = 0;  // step k0 produces u^{k0+1}: slot (k0+1) - k0 - 1 = 0
-        fo.ddir = 1;
-        advance(c, sf, k0, k1 - k0, fo);
         c.base = adj;
         StepOpts ao;
         ao.mode = kImaging;

@@ -465,3 +465,18 @@ def test_anisotropic_spacing_matches_oracle_and_variants_agree(so):
                                                                   tile=(0, 32, 4))):
         out = gpu_forward(cs, **opt)
         assert torch.equal(out["u"], base["u"]) and torch.equal(out["rec"], base["rec"]), opt
+
+
+@pytest.mark.parametrize("opt", [dict(variant=L.FD_VARIANT_NAIVE), dict(variant=L.FD_VARIANT_STREAM),
+                                 dict(variant=L.FD_VARIANT_TBLOCK, tblock=2)])
+def test_full_storage_gradient_equals_checkpointed(opt):
+    """ckpt_every >= nt stores the whole time axis (no recomputation): same J,
+    gradient and residual bit for bit, and the same vector-Jacobian product."""
+    cs, d_obs = gradient_case()
+    args = (cs["v"].to(DEV), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"],
+            torch.from_numpy(cs["amp"]).to(DEV), cs["rec"])
+    kw = dict(sponge=cs["sponge"], vref=cs["vref"], **opt)
+    Jf, gf, rf = api.gradient(*args, torch.from_numpy(d_obs).to(DEV), ckpt_every=cs["nt"] + 5, **kw)
+    Jc, gc, rc = api.gradient(*args, torch.from_numpy(d_obs).to(DEV), ckpt_every=13, **kw)
+    assert Jf == Jc and torch.equal(gf, gc) and torch.equal(rf, rc)
+    assert torch.equal(api.vjp(*args, rc, ckpt_every=cs["nt"], **kw), api.vjp(*args, rc, ckpt_every=13, **kw))
