@@ -73,8 +73,9 @@ def _load():
         lib.or_adjoint.argtypes = [P, D, D, D]
         lib.or_vjp.argtypes = [P, D, D, D, D]
         lib.or_gradient.argtypes = [P, D, D, D, D, D]
+        lib.or_born.argtypes = [P, D, D, D]
         for f in ("or_weights", "or_laplacian", "or_damp", "or_forward", "or_adjoint",
-                  "or_vjp", "or_gradient"):
+                  "or_vjp", "or_gradient", "or_born"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
     return _lib
@@ -195,6 +196,15 @@ def vjp(prob: Problem, amp, y):
     gm = np.zeros(prob.shape)
     _check(_load().or_vjp(prob.ref(), _dptr(a), _dptr(y), _dptr(gv), _dptr(gm)), "vjp")
     return gv, gm
+
+
+def born(prob: Problem, amp, dv):
+    """Born (linearised) traces [nt][nr] for a velocity perturbation dv, zero initial state."""
+    a = np.ascontiguousarray(np.asarray(amp, dtype=np.float64).reshape(prob.nt, len(prob.src)))
+    dv = np.ascontiguousarray(np.asarray(dv, dtype=np.float64).reshape(prob.shape))
+    dd = np.zeros((prob.nt, len(prob.rec)), dtype=np.float64)
+    _check(_load().or_born(prob.ref(), _dptr(a), _dptr(dv), _dptr(dd)), "born")
+    return dd
 
 
 def gradient(prob: Problem, amp, d_obs):

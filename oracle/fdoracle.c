@@ -42,6 +42,11 @@
  * the transposed system is solved backward in time:
  *   lambda^k = A^{-1} (B lambda^{k+1} + C lambda^{k+2} + P_r^T y[k-1]),  k = nt..1,
  * lambda^{nt+1} = lambda^{nt+2} = 0, and (F^T y)[k-1][s] = 2 dt^2 lambda^k(s).
+ * Born (linearised) modelling: differentiating the step with respect to m
+ * (dA = 2 dm, dB = 4 dm, dC = -2 dm) gives the perturbation wavefield
+ *   A du^k = B du^{k-1} + C du^{k-2} - 2 dm (u^k - 2u^{k-1} + u^{k-2}),
+ * du^0 = du^{-1} = 0, and the perturbed traces dd[n] = P_r du^{n+1}; for a
+ * velocity perturbation dv, dm = -2 dv / v^3.
  * Gradient of J = 1/2 sum (d - d_obs)^2 (plain sum):
  *   dJ/dm(x) = -2 sum_{k=1..nt} lambda^k(x) (u^k - 2u^{k-1} + u^{k-2})(x),
  *   dJ/dv = dJ/dm * (-2 / v^3).
@@ -469,6 +474,51 @@ int or_vjp(const or_problem *p, const double *amp, const double *y, double *grad
     free(uc);
     free(up);
     free(gm);
+    return rc;
+}
+
+/*
+ * Born modelling: traces dd [nt][nr] of the perturbation wavefield for a
+ * velocity perturbation dv (N^d), zero initial state, source samples amp.
+ * The background and the perturbation advance together, step by step.
+ */
+int or_born(const or_problem *p, const double *amp, const double *dv, double *dd)
+{
+    work w;
+    int rc = work_init(p, &w);
+    if (rc) { work_free(&w); return rc; }
+    int64_t N = w.g.npts;
+    double *u[3], *du[3];
+    for (int i = 0; i < 3; ++i) {
+        u[i] = (double *)calloc(N, sizeof(double));
+        du[i] = (double *)calloc(N, sizeof(double));
+    }
+    double *dm = (double *)malloc(sizeof(double) * N);
+    if (!u[0] || !u[1] || !u[2] || !du[0] || !du[1] || !du[2] || !dm) rc = -2;
+    if (!rc) {
+        for (int64_t i = 0; i < N; ++i) dm[i] = -2.0 * dv[i] / (p->v[i] * p->v[i] * p->v[i]);
+        double dt2 = p->dt * p->dt;
+        /* u[0] = u^{k-2}, u[1] = u^{k-1}, u[2] <- u^k; du alike */
+        for (int64_t n = 0; n < p->nt; ++n) {
+            leapfrog_step(&w.g, w.c, w.M, p->dt, w.m, w.damp, u[1], u[0], u[2]);
+            if (amp)
+                for (int s = 0; s < p->ns; ++s) {
+                    double a = 2.0 * dt2 * amp[n * p->ns + s];
+                    spread(&w.sp[s], a, p->dt, w.m, w.damp, u[2]);
+                }
+            leapfrog_step(&w.g, w.c, w.M, p->dt, w.m, w.damp, du[1], du[0], du[2]);
+            for (int64_t i = 0; i < N; ++i)
+                du[2][i] += -2.0 * dm[i] * (u[2][i] - 2.0 * u[1][i] + u[0][i])
+                            / (p->dt * w.damp[i] + 2.0 * w.m[i]);
+            if (dd)
+                for (int r = 0; r < p->nr; ++r) dd[n * p->nr + r] = sample(&w.rp[r], du[2]);
+            double *t = u[0]; u[0] = u[1]; u[1] = u[2]; u[2] = t;
+            t = du[0]; du[0] = du[1]; du[1] = du[2]; du[2] = t;
+        }
+    }
+    for (int i = 0; i < 3; ++i) { free(u[i]); free(du[i]); }
+    free(dm);
+    work_free(&w);
     return rc;
 }
 

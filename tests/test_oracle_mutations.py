@@ -32,6 +32,9 @@ MUTATIONS = {
     "interp_spread_unweighted": ("u[i] += s->w[j] * a / (dt * damp[i] + 2.0 * m[i]);", "u[i] += a / (dt * damp[i] + 2.0 * m[i]);"),
     "interp_cell_above": ("base[a + g->first] = i;", "base[a + g->first] = i > 0 ? i - 1 : i;"),
     "imaging_first_difference": ("(uk[i] - 2.0 * uk1[i] + uk2[i])", "(uk[i] - uk1[i])"),
+    "born_source_sign": ("du[2][i] += -2.0 * dm[i] * (u[2][i]", "du[2][i] += 2.0 * dm[i] * (u[2][i]"),
+    "born_first_difference": ("(u[2][i] - 2.0 * u[1][i] + u[0][i])", "(u[2][i] - u[1][i])"),
+    "born_dm_power": ("dm[i] = -2.0 * dv[i] / (p->v[i] * p->v[i] * p->v[i]);", "dm[i] = -2.0 * dv[i] / (p->v[i] * p->v[i]);"),
     "sponge_off_by_one": ("if (i < L) delta = (double)(L - i);", "if (i < L) delta = (double)(L - i - 1);"),
     "dt_squared_missing": ("double dt2 = dt * dt;\n#pragma omp parallel for schedule(static)\n    for (int64_t i0 = 0; i0 < g->n[0]; ++i0)\n        for (int64_t i1 = 0; i1 < g->n[1]; ++i1)\n            for (int64_t i2 = 0; i2 < g->n[2]; ++i2) {\n                int64_t i = (i0 * g->n[1] + i1) * g->n[2] + i2;\n                double tcse",
                            "double dt2 = dt;\n#pragma omp parallel for schedule(static)\n    for (int64_t i0 = 0; i0 < g->n[0]; ++i0)\n        for (int64_t i1 = 0; i1 < g->n[1]; ++i1)\n            for (int64_t i2 = 0; i2 < g->n[2]; ++i2) {\n                int64_t i = (i0 * g->n[1] + i1) * g->n[2] + i2;\n                double tcse"),
@@ -55,6 +58,7 @@ def _checks():
     yield lambda: pins.test_offgrid_receivers_read_multilinear_fields_exactly(4)
     yield lambda: pins.test_offgrid_source_spreads_unit_mass_at_its_position((4.25, 5.5, 6.75))
     yield lambda: pins.test_offgrid_dot_product_fp64((40, 36))
+    yield lambda: pins.test_born_is_the_derivative_of_the_forward_map(False)
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

@@ -547,3 +547,37 @@ def test_offgrid_gradient_central_finite_difference_fp64():
     fd = (J_at(v + eps * dv) - J_at(v - eps * dv)) / (2 * eps)
     an = float((gv * dv).sum())
     assert abs(fd - an) <= 1e-7 * abs(an)
+
+
+# ---------------------------------------------------------------- Born modelling
+def _born_problem(shape=(20, 18, 22), nt=50, offgrid=False):
+    v = synth.smooth_velocity(shape, seed=1711, sigma=3.0).numpy().astype(np.float64)
+    dt = 0.8 * 0.4529 * 10.0 / v.max()
+    src = np.array([[9.6, 8.3, 6.45]]) if offgrid else synth.centre_source(shape, depth=6)
+    rec = synth.offgrid_receiver_line(shape, 9, depth=6.7) if offgrid else synth.receiver_line(shape, 9, depth=6)
+    w = synth.ricker(nt, dt, 60.0).astype(np.float64)[:, None]
+    mk = lambda vv: oracle.Problem(vv, [10.0] * 3, 8, nt, dt, sponge=5, vref=4500.0, src=src, rec=rec)
+    dv = synth.smooth_velocity(shape, seed=1712, sigma=2.0).numpy().astype(np.float64) - 3000.0
+    return v, w, dv, mk
+
+
+@pytest.mark.parametrize("offgrid", [False, True])
+def test_born_is_the_derivative_of_the_forward_map(offgrid):
+    """Central difference of the traces along dv: agrees with Born to O(eps^2)."""
+    v, w, dv, mk = _born_problem(offgrid=offgrid)
+    dd = oracle.born(mk(v), w, dv)
+    eps = 1e-4
+    fd = (oracle.forward(mk(v + eps * dv), amp=w)["rec"] - oracle.forward(mk(v - eps * dv), amp=w)["rec"]) / (2 * eps)
+    assert np.linalg.norm(dd) > 0
+    assert np.linalg.norm(fd - dd) <= 1e-7 * np.linalg.norm(dd)
+
+
+def test_born_is_the_transpose_of_the_vector_jacobian_product():
+    """<J dv, y> = <dv, J^T y>, J^T y from the adjoint-state gradient (itself pinned)."""
+    v, w, dv, mk = _born_problem(offgrid=True)
+    prob = mk(v)
+    y = np.random.default_rng(14).standard_normal((prob.nt, len(prob.rec)))
+    lhs = float((oracle.born(prob, w, dv) * y).sum())
+    gv, _ = oracle.vjp(prob, w, y)
+    rhs = float((dv * gv).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
