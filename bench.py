@@ -299,6 +299,24 @@ def offgrid_rates(cs):
     return out
 
 
+def born_rate(reps=2, warmup=1):
+    """Born modelling on the headline grid (256^3 so 8, 500 steps, 256 receivers):
+    GPts/s of the linearised operator (one point-step advances the background
+    and the perturbation wavefield)."""
+    import synth
+    from paper_1707_02347_amd import api
+
+    cs = workload("cfg2")
+    rec = synth.receiver_line(cs["v"].shape, 256, depth=20)
+    dv = 0.05 * cs["v"] * synth.blob_velocity(cs["v"], amp=1.0, width_frac=1.0 / 16.0).sub(cs["v"]).div(cs["v"])
+    run = lambda: api.born(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], rec, dv,
+                           sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg2"))
+    med, _, _ = _timed(run, reps, warmup)
+    npts = int(np.prod(cs["v"].shape))
+    return {"gpts": round(npts * cs["nt"] / (med * 1e-3) / 1e9, 2), "ms": round(med, 1),
+            "config": "256^3 so8, 500 steps, 256 receivers, dv = 5 % Gaussian blob of width N/16"}
+
+
 def gradient_rate(reps=2, warmup=1, off_grid=False, ckpt_every=50):
     """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
     import torch
@@ -497,6 +515,8 @@ def main():
         # the whole time axis stored (1000 second differences, 64 GB) instead of
         # checkpoints every 50 steps: no recomputation sweep
         line["cfg4_full_storage_gradients_per_s"] = gradient_rate(ckpt_every=1000)["gradients_per_s"]
+        print("# Born modelling", file=sys.stderr, flush=True)
+        line["born_modelling"] = born_rate()
         print("# cfg5", file=sys.stderr, flush=True)
         try:
             line["cfg5_batched"] = batch_rates()

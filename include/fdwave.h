@@ -108,6 +108,7 @@ extern "C" {
 #define FD_OP_ADJOINT 1
 #define FD_OP_GRADIENT 2
 #define FD_OP_VJP 3
+#define FD_OP_BORN 4
 
 /* Grid: extents, spacing, space order and sponge. */
 typedef struct fd_grid {
@@ -231,6 +232,25 @@ int fd_gradient(const fd_grid *grid, const fd_time *time, const float *v,
 int fd_vjp(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
            const fd_points *rec, float *grad_v, void *workspace, size_t ws_bytes,
            const fd_options *opts, void *stream);
+
+/*
+ * Born (linearised) modelling: the traces dd = (dd/dv) dv of the map v -> d for
+ * a velocity perturbation dv, zero initial state.  Differentiating the step with
+ * respect to m = 1/v^2 (paper Sec. 6.3.1 update; dm = -2 dv / v^3) gives the
+ * perturbation wavefield the same recurrence driven by the volume source
+ * A^{-1} (-2 dm (u^k - 2u^{k-1} + u^{k-2})), u the background wavefield; each step
+ * advances the background (saving its second difference) and then the
+ * perturbation, whose update folds the source in as (num + s d2) / (1 + eta),
+ * s = 2 dv / v.  fd_vjp is its transpose.
+ *   dv       DEVICE [N] FP32 velocity perturbation (m/s).
+ *   src->amp DEVICE [nt][ns] source wavelet of the background.
+ *   rec_out  DEVICE [nt][nr] perturbed traces (may be NULL if nr == 0).
+ * Workspace: fd_workspace_size(..., FD_OP_BORN) (ten fields and the tables).
+ * Errors as fd_forward; FD_EINVAL if dv is NULL.
+ */
+int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const float *dv,
+            const fd_points *src, const fd_points *rec, float *rec_out, void *workspace,
+            size_t ws_bytes, const fd_options *opts, void *stream);
 
 /*
  * Autotuner: times candidate kernels (variant, tile, time-block depth) for a

@@ -41,6 +41,7 @@ FD_OP_FORWARD = 0
 FD_OP_ADJOINT = 1
 FD_OP_GRADIENT = 2
 FD_OP_VJP = 3
+FD_OP_BORN = 4
 
 FD_BATCH_GRAPH = 1
 
@@ -119,6 +120,9 @@ SYMBOLS = {
     "fd_vjp": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.POINTER(fd_points),
                          C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.c_size_t,
                          C.POINTER(fd_options), C.c_void_p]),
+    "fd_born": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.c_void_p, C.POINTER(fd_points),
+                          C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(fd_options),
+                          C.c_void_p]),
     "fd_autotune": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.POINTER(fd_options), C.c_void_p,
                               C.c_size_t, C.c_void_p]),
     "fd_batch_workspace_size": (C.c_size_t, [C.c_int, C.POINTER(fd_shot), C.c_int]),
@@ -177,6 +181,10 @@ def fd_gradient(grid, time, v, src, rec, grad_v, misfit, residual, workspace, ws
 
 def fd_vjp(grid, time, v, src, rec, grad_v, workspace, ws_bytes, opts, stream):
     return load().fd_vjp(grid, time, v, src, rec, grad_v, workspace, ws_bytes, opts, stream)
+
+
+def fd_born(grid, time, v, dv, src, rec, rec_out, workspace, ws_bytes, opts, stream):
+    return load().fd_born(grid, time, v, dv, src, rec, rec_out, workspace, ws_bytes, opts, stream)
 
 
 def fd_autotune(grid, time, inout, workspace, ws_bytes, stream):

@@ -127,6 +127,30 @@ def vjp(v, h, so, nt, dt, src_idx, src_amp, rec_idx, y, sponge=0, vref=1500.0, v
     return gv
 
 
+def born(v, h, so, nt, dt, src_idx, src_amp, rec_idx, dv, sponge=0, vref=1500.0, variant=0,
+         tile=(0, 0, 0), tblock=0, flags=0):
+    """Born (linearised) traces (dd/dv) dv [nt][nr] for a velocity perturbation dv."""
+    v = _dev_f32(v, "v")
+    shape = tuple(v.shape)
+    nd = len(shape)
+    dv = _dev_f32(dv, "dv")
+    if tuple(dv.shape) != shape:
+        raise ValueError("dv must have the shape of v")
+    grid = L.make_grid(shape, h, so, sponge, vref)
+    tm = L.make_time(nt, dt)
+    src = L.Points(src_idx, _dev_f32(src_amp, "src_amp"), nd)
+    rec = L.Points(rec_idx, None, nd)
+    o = _opts(variant, tile, tblock, 0, flags)
+    dd = torch.zeros((int(nt), rec.n), dtype=torch.float32, device=v.device)
+    nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
+                                 L.FD_OP_BORN)
+    ws = _workspace(nbytes, v.device)
+    rc = L.fd_born(C.byref(grid), C.byref(tm), L._ptr(v), L._ptr(dv), C.byref(src.s), C.byref(rec.s),
+                   L._ptr(dd) if rec.n else None, L._ptr(ws), ws.numel(), C.byref(o), L._stream(v.device))
+    L._check(rc, "fd_born")
+    return dd
+
+
 def autotune(shape, h, so, dt, device="cuda", sponge=0, vref=1500.0, nt=8, variant=0, tblock=0):
     """Run the library's autotuner for this grid; returns the chosen options as a dict."""
     grid = L.make_grid(shape, h, so, sponge, vref)

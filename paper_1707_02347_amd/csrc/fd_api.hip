@@ -303,10 +303,12 @@ struct PtsSpec {
     bool interp = false;
 };
 
+constexpr int kMaxFields = 12;
+
 struct Layout {
     float *q = nullptr;
     float *prof = nullptr;          // px | py | pz
-    float *fields[8] = {};          // spare fields (ping-pong, state)
+    float *fields[kMaxFields] = {}; // spare fields (ping-pong, state)
     int nfields = 0;
     TableBufs src{}, rec{};
     float *vstat = nullptr;
@@ -351,12 +353,13 @@ Layout layout(void *ws, const Dims &d, int64_t nt, const PtsSpec &S, const PtsSp
     Layout L;
     L.q = cv.take<float>(d.Np);
     L.prof = cv.take<float>((size_t)d.nx + d.ny + d.nz);
-    L.nfields = nfields;
-    for (int i = 0; i < nfields; ++i) L.fields[i] = cv.take<float>(d.Np);
+    L.nfields = std::min(nfields, kMaxFields);
+    for (int i = 0; i < L.nfields; ++i) L.fields[i] = cv.take<float>(d.Np);
     L.src = carve_table(cv, d.nx, S, nt);
     L.rec = carve_table(cv, d.nx, R, nt);
     L.vstat = cv.take<float>(3 * kStatBlocks);
     L.rpart = cv.take<double>(kStatBlocks);
+    if (op == FD_OP_BORN) L.seg = cv.take<float>(d.Np);  // the background's second difference
     if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
         L.nck = nt > 0 ? (int)((nt + K - 1) / K) : 0;
         L.ckpt = cv.take<float>((size_t)std::max(L.nck, 1) * 2 * d.Np);
@@ -376,6 +379,7 @@ int fields_needed(int op)
     switch (op) {
     case FD_OP_FORWARD:
     case FD_OP_ADJOINT: return 4;
+    case FD_OP_BORN: return 9;  // background 4, perturbation 4, s
     default: return 9;
     }
 }
@@ -1247,7 +1251,7 @@ size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_poin
 {
     Dims d;
     if (make_dims(grid, d) || !time || time->nt < 0) return 0;
-    if (op < FD_OP_FORWARD || op > FD_OP_VJP) return 0;
+    if (op < FD_OP_FORWARD || op > FD_OP_BORN) return 0;
     // the tables of both point sets are laid out alike, so the order (which
     // set injects) does not change the size
     Layout L = layout(nullptr, d, time->nt, spec_of(d, src), spec_of(d, rec), op, fields_needed(op),
@@ -1321,6 +1325,64 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
         }
         record_last(c.plan);
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(src_out, c.nt * ns, c.s);
+        return FD_OK;
+    });
+}
+
+int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const float *dv,
+            const fd_points *src, const fd_points *rec, float *rec_out, void *workspace,
+            size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        Ctx c;
+        int rc = validate_common(grid, time, v, c.d);
+        if (rc) return rc;
+        if (!dv) return FD_EINVAL;
+        if ((rc = check_points(c.d, src, true, time->nt))) return rc;
+        if ((rc = check_points(c.d, rec, false, time->nt))) return rc;
+        const int ns = src ? src->n : 0, nr = rec ? rec->n : 0;
+        if (nr > 0 && time->nt > 0 && !rec_out) return FD_EINVAL;
+        c.nt = time->nt;
+        c.dt = time->dt;
+        c.s = (hipStream_t)stream;
+        c.ex.s = c.s;
+        if ((rc = make_plan(c.d, opts, c.plan))) return rc;
+        const PtsSpec S = spec_of(c.d, src), R = spec_of(c.d, rec);
+        c.L = layout(nullptr, c.d, c.nt, S, R, FD_OP_BORN, fields_needed(FD_OP_BORN), 1);
+        if ((rc = ws_check(workspace, ws_bytes, c.L.bytes))) return rc;
+        c.L = layout(workspace, c.d, c.nt, S, R, FD_OP_BORN, fields_needed(FD_OP_BORN), 1);
+        const uint32_t flags = opts ? opts->flags : 0u;
+        if ((rc = prepare(c, grid, v, src, 1.0f, rec, flags))) return rc;
+        const int64_t N = c.d.Np, rows = (int64_t)c.d.nx * c.d.ny;
+        float *bs = c.L.fields[8];
+        FDW_HIP(launch_born_coef(v, dv, bs, rows, c.d.nz, c.d.nzp, c.s));
+        for (int i = 0; i < 8; ++i) FDW_HIP(launch_zero(c.L.fields[i], N * 4, c.s));
+        // background: sources inject, no recording, the second difference of
+        // each new level goes to slot 0; perturbation: the Born source, no
+        // injection, receivers record
+        SweepArgs bg = c.base;
+        bg.amp = src ? src->amp : nullptr;
+        bg.rec = as_table(c.L.rec, nr, 0, false);
+        SweepArgs pb = c.base;
+        pb.inj = as_table(c.L.src, ns, 0, true);
+        pb.rec_out = rec_out;
+        pb.bs = bs;
+        State sb{c.L.fields[0], c.L.fields[1], {c.L.fields[2], c.L.fields[3], nullptr}, 2};
+        State sp{c.L.fields[4], c.L.fields[5], {c.L.fields[6], c.L.fields[7], nullptr}, 2};
+        StepOpts fo, bo;
+        fo.mode = kSaveD2;
+        bo.mode = kBorn;
+        fo.dslot_first = bo.dslot_first = 0;
+        fo.ddir = bo.ddir = 0;
+        for (int64_t k = 0; k < c.nt; ++k) {
+            c.base = bg;
+            advance(c, sb, k, 1, fo);
+            c.base = pb;
+            advance(c, sp, k, 1, bo);
+        }
+        gather_traces(c, c.L.rec, nr, pb.rec.cnt, rec_out, 1.0f);
+        record_last(c.plan);
+        if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, c.nt * nr, c.s);
         return FD_OK;
     });
 }

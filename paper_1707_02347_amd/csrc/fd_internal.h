@@ -76,6 +76,8 @@ struct SweepArgs {
     int64_t dslot0;
     int ddir;
     double *g;        // imaging accumulator (FP64, N)
+    const float *bs;  // Born: scattering coefficient 2 dv / v (N); d2 slot dslot0 holds
+                      // the background's second difference
     // tiling of the launch
     int lx;           // planes per workgroup along x
     int ntz, nty, ntx;
@@ -103,7 +105,11 @@ constexpr int kPtsCap = 512;
 constexpr int kStageMin = 32;
 constexpr bool points_stageable(int PY, int NW) { return NW < 16 && PY <= 4; }
 
-enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2 };
+// kBorn: the perturbation wavefield of Born modelling, whose update carries
+// the volume source s * d2 inside the division: (num + s d2) / (1 + eta), with
+// s = 2 dv / v and d2 the background's second difference at the same step
+// (single-step passes only).
+enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2, kBorn = 3 };
 
 // The damped update's division u = num / (1 + eta), taken only where eta != 0
 // (the sponge), as num times the hardware reciprocal of 1 + eta (v_rcp_f32,
@@ -165,6 +171,8 @@ hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2,
 // Preparation / reduction kernels.
 // q = v^2 dt^2 from the dense caller layout (rows of nz) into the padded
 // internal layout (rows of nzp, padding zero).
+hipError_t launch_born_coef(const float *v, const float *dv, float *s, int64_t rows, int nz, int nzp,
+                            hipStream_t st);
 hipError_t launch_make_q(const float *v, float *q, int64_t rows, int nz, int nzp, double dt2,
                          hipStream_t s);
 // Copy rows of nz floats between layouts of row pitch spitch and dpitch (the

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_naive_step(SweepArgs a)
     }
     const float qv = a.q[c];
     const float eta = qv * (a.px[x] + (a.py[y] + a.pz[z]));
-    const float num = fmaf(qv, lap, fmaf(eta - 1.0f, a.um[c], 2.0f * uc));
+    float num = fmaf(qv, lap, fmaf(eta - 1.0f, a.um[c], 2.0f * uc));
+    if (a.bs) num = fmaf(a.bs[c], a.d2[a.dslot0 * (int64_t)a.nx * a.sxy + c], num);  // Born source
     a.o1[c] = damped(num, eta);
 }
 
@@ -212,6 +213,27 @@ hipError_t launch_make_q(const float *v, float *q, int64_t rows, int nz, int nzp
                          hipStream_t s)
 {
     hipLaunchKernelGGL(k_make_q, dim3(4096), dim3(256), 0, s, v, q, rows, nz, nzp, dt2);
+    return hipGetLastError();
+}
+
+// Born scattering coefficient s = 2 dv / v (FP64, rounded once), padded rows.
+__global__ void k_born_coef(const float *v, const float *dv, float *s, int64_t rows, int nz,
+                            int nzp)
+{
+    const int64_t n = rows * nzp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / nzp;
+        const int z = (int)(i - r * nzp);
+        const int64_t j = r * nz + z;
+        s[i] = (z < nz) ? (float)(2.0 * (double)dv[j] / (double)v[j]) : 0.0f;
+    }
+}
+
+hipError_t launch_born_coef(const float *v, const float *dv, float *s, int64_t rows, int nz, int nzp,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_born_coef, dim3(4096), dim3(256), 0, st, v, dv, s, rows, nz, nzp);
     return hipGetLastError();
 }
 

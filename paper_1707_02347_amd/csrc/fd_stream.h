@@ -184,6 +184,8 @@ struct StreamKernel {
     };
 
     static constexpr bool IMG = (MODE == kImaging);
+    static constexpr bool BORN = (MODE == kBorn);
+    static_assert(!BORN || T == 1, "Born passes are single-step");
     struct Pre {
         float head[PY];
         float halo[G::HS];
@@ -193,6 +195,9 @@ struct StreamKernel {
         // differences at every level's plane
         double g[IMG ? PY : 1];
         float d2[IMG ? T : 1][IMG ? PY : 1];
+        // Born: the scattering coefficient and the background's second
+        // difference at level 1's plane
+        float bs[BORN ? PY : 1], bd[BORN ? PY : 1];
     };
 
     struct Thread {
@@ -536,6 +541,15 @@ struct StreamKernel {
 #pragma unroll
             for (int r = 0; r < PY; ++r) P.q[t - 1][r] = bload<LP>(rq, th.bo[r]);
         }
+        if constexpr (BORN) {
+            const auto rs = plane_rsrc(a.bs, c1, a.sxy, l1);
+            const auto rd = plane_rsrc(a.d2 + a.dslot0 * (int64_t)a.nx * a.sxy, c1, a.sxy, l1);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                P.bs[r] = bload<LP>(rs, th.bo[r]);
+                P.bd[r] = bload<LP>(rd, th.bo[r]);
+            }
+        }
         if constexpr (IMG) {
             // only planes this chunk owns are read (and later written); offsets
             // of points outside the output tile are beyond the plane
@@ -629,7 +643,8 @@ struct StreamKernel {
                 if constexpr (t == 1) up = P.up1[r];
                 else up = qu[t - 2][r][pj<PH>(0)];
                 const float eta = qv * (pxv + th.pyz[r]);
-                const float num = fmaf(qv, lap, fmaf(eta - 1.0f, up, 2.0f * uc));
+                float num = fmaf(qv, lap, fmaf(eta - 1.0f, up, 2.0f * uc));
+                if constexpr (BORN) num = fmaf(P.bs[r], P.bd[r], num);
                 out[r] = active ? damped(num, eta) : 0.0f;
             }
             const int step = a.step0 + t - 1;

@@ -15,27 +15,28 @@
     X(1, 1, 16, 2, 0, 0) X(1, 1, 8, 4, 1, FDW_AG) X(1, 1, 8, 4, 2, FDW_AG)                 \
     X(1, 1, 4, 8, 1, FDW_AG) X(1, 1, 4, 8, 2, FDW_AG) X(1, 2, 4, 8, 0, FDW_AG)             \
     X(1, 2, 2, 16, 0, FDW_AG) X(1, 3, 4, 8, 0, FDW_G) X(1, 3, 2, 16, 0, FDW_G)              \
-    X(1, 4, 4, 8, 0, 0) X(1, 4, 2, 16, 0, 0) X(1, 2, 4, 8, 1, FDW_G) X(1, 2, 4, 8, 2, FDW_G)
+    X(1, 4, 4, 8, 0, 0) X(1, 4, 2, 16, 0, 0) X(1, 2, 4, 8, 1, FDW_G) X(1, 2, 4, 8, 2, FDW_G)             \
+    X(1, 1, 4, 8, 3, FDW_A)
 
 #define FDW_CONFIGS_M2(X)                                                                  \
     X(2, 1, 8, 4, 0, FDW_AG) X(2, 1, 4, 4, 0, FDW_AG) X(2, 1, 4, 8, 0, FDW_AG)             \
     X(2, 1, 16, 2, 0, 0) X(2, 1, 8, 4, 1, FDW_AG) X(2, 1, 8, 4, 2, FDW_AG)                 \
     X(2, 1, 4, 8, 1, FDW_AG) X(2, 1, 4, 8, 2, FDW_AG) X(2, 2, 4, 8, 0, FDW_AG)             \
     X(2, 2, 2, 16, 0, FDW_AG) X(2, 3, 4, 8, 0, FDW_G) X(2, 3, 2, 16, 0, FDW_G)              \
-    X(2, 4, 2, 16, 0, 0) X(2, 2, 4, 8, 1, FDW_G) X(2, 2, 4, 8, 2, FDW_G)
+    X(2, 4, 2, 16, 0, 0) X(2, 2, 4, 8, 1, FDW_G) X(2, 2, 4, 8, 2, FDW_G) X(2, 1, 4, 8, 3, FDW_A)
 
 #define FDW_CONFIGS_M3(X)                                                                  \
     X(3, 1, 8, 4, 0, FDW_AG) X(3, 1, 8, 4, 1, FDW_AG) X(3, 1, 8, 4, 2, FDW_AG)             \
-    X(3, 1, 4, 8, 0, FDW_AG) X(3, 1, 4, 8, 1, FDW_AG) X(3, 1, 4, 8, 2, FDW_AG)
+    X(3, 1, 4, 8, 0, FDW_AG) X(3, 1, 4, 8, 1, FDW_AG) X(3, 1, 4, 8, 2, FDW_AG) X(3, 1, 4, 8, 3, FDW_A)
 #define FDW_CONFIGS_M5(X)                                                                  \
     X(5, 1, 8, 4, 0, FDW_AG) X(5, 1, 8, 4, 1, FDW_AG) X(5, 1, 8, 4, 2, FDW_AG)             \
-    X(5, 1, 4, 4, 0, FDW_AG) X(5, 1, 4, 4, 1, FDW_AG) X(5, 1, 4, 4, 2, FDW_AG)
+    X(5, 1, 4, 4, 0, FDW_AG) X(5, 1, 4, 4, 1, FDW_AG) X(5, 1, 4, 4, 2, FDW_AG) X(5, 1, 4, 4, 3, FDW_A)
 #define FDW_CONFIGS_M6(X)                                                                  \
     X(6, 1, 8, 4, 0, FDW_AG) X(6, 1, 8, 4, 1, FDW_AG) X(6, 1, 8, 4, 2, FDW_AG)             \
-    X(6, 1, 4, 4, 0, FDW_AG) X(6, 1, 4, 4, 1, FDW_AG) X(6, 1, 4, 4, 2, FDW_AG)
+    X(6, 1, 4, 4, 0, FDW_AG) X(6, 1, 4, 4, 1, FDW_AG) X(6, 1, 4, 4, 2, FDW_AG) X(6, 1, 4, 4, 3, FDW_A)
 #define FDW_CONFIGS_M7(X)                                                                  \
     X(7, 1, 8, 4, 0, FDW_AG) X(7, 1, 8, 4, 1, FDW_AG) X(7, 1, 8, 4, 2, FDW_AG)             \
-    X(7, 1, 4, 4, 0, FDW_AG) X(7, 1, 4, 4, 1, FDW_AG) X(7, 1, 4, 4, 2, FDW_AG)
+    X(7, 1, 4, 4, 0, FDW_AG) X(7, 1, 4, 4, 1, FDW_AG) X(7, 1, 4, 4, 2, FDW_AG) X(7, 1, 4, 4, 3, FDW_A)
 
 #define FDW_CONFIGS_M4(X)                                                                  \
     X(4, 1, 8, 4, 0, FDW_AG) X(4, 1, 4, 4, 0, FDW_AG) X(4, 1, 16, 2, 0, 0)                 \
@@ -44,10 +45,10 @@
     X(4, 1, 4, 8, 2, FDW_AG) X(4, 2, 4, 8, 0, FDW_A) X(4, 2, 2, 16, 0, FDW_AG)            \
     X(4, 3, 4, 8, 0, 0) X(4, 3, 2, 16, 0, 0)                      \
     X(4, 2, 4, 8, 1, FDW_G) X(4, 2, 4, 8, 2, FDW_G) X(4, 2, 2, 16, 1, FDW_G)              \
-    X(4, 2, 2, 16, 2, 0)
+    X(4, 2, 2, 16, 2, 0) X(4, 1, 4, 8, 3, FDW_A)
 
 #define FDW_CONFIGS_M8(X)                                                                  \
     X(8, 1, 8, 4, 0, FDW_AG) X(8, 1, 4, 4, 0, FDW_AG) X(8, 1, 8, 2, 0, 0)                  \
     X(8, 1, 4, 8, 0, FDW_AG) X(8, 1, 2, 16, 0, 0) X(8, 1, 8, 4, 1, FDW_AG)                 \
     X(8, 1, 8, 4, 2, FDW_AG) X(8, 1, 4, 4, 1, FDW_AG) X(8, 1, 4, 4, 2, FDW_AG)             \
-    X(8, 2, 4, 8, 0, FDW_AG) X(8, 2, 4, 8, 1, FDW_G)
+    X(8, 2, 4, 8, 0, FDW_AG) X(8, 2, 4, 8, 1, FDW_G) X(8, 1, 4, 4, 3, FDW_A)

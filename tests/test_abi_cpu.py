@@ -175,6 +175,18 @@ def test_offgrid_points_grow_the_workspace():
         assert b >= a + 2 * 100 * 8 * 4
 
 
+def test_born_validates_on_host_and_sizes_its_workspace():
+    g, t = _grid(), L.make_time(10, 1e-3)
+    src, rec = L.Points(np.array([[1, 2, 3]]), None, 3), L.Points(np.array([[2, 2, 2]]), None, 3)
+    fwd = L.fd_workspace_size(C.byref(g), C.byref(t), C.byref(src.s), C.byref(rec.s), None, L.FD_OP_FORWARD)
+    born = L.fd_workspace_size(C.byref(g), C.byref(t), C.byref(src.s), C.byref(rec.s), None, L.FD_OP_BORN)
+    N4 = 32 * 30 * 64 * 4
+    assert born >= fwd + 6 * N4  # perturbation pair and spares, the coefficient and the second difference
+    rc = L.fd_born(C.byref(g), C.byref(t), C.c_void_p(0x1000), None, C.byref(src.s), C.byref(rec.s),
+                   C.c_void_p(0x2000), C.c_void_p(0x10000), born, None, None)
+    assert rc == L.FD_EINVAL  # no perturbation
+
+
 def test_gradient_and_adjoint_validate_on_host():
     g, t = _grid(), L.make_time(10, 1e-3)
     src = L.Points(np.array([[1, 2, 3]]), None, 3)
