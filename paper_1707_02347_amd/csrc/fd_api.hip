@@ -1809,8 +1809,27 @@ void batch_chunk(Ctx &c, const fd_options &o)
 // same kernel configuration and Laplacian form become one grouped
 // launch over all their tiles, other ops run as recorded.  Shots are
 // independent, so any interleaving that keeps each shot's order is valid.
-int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_t max_entries,
-               bool graph, hipStream_t s)
+// Streams and events of a batch's lanes, released on every exit path (a
+// stream or event still in use is released by the runtime once its work ends).
+struct LaneSet {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    ~LaneSet()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t t : streams) (void)hipStreamDestroy(t);
+    }
+    hipEvent_t event()
+    {
+        hipEvent_t e = nullptr;
+        FDW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        events.push_back(e);
+        return e;
+    }
+};
+
+int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m,
+               GroupEntry *dev_entries, size_t max_entries, bool graph, hipStream_t s)
 {
     struct Launch {
         bool grouped;
@@ -1823,6 +1842,14 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
         int shot, idx;
         int grid;
     };
+    // Lanes: a grouped launch only holds shots of one space order, so the work
+    // of each space order is a chain independent of the others.  Each lane
+    // gets a stream of its own, forked from and joined back to the issuing
+    // stream, so that the launches of different orders overlap (one order's
+    // tail of workgroups leaves CUs that another's launch can fill).
+    std::map<int, int> lane_of;
+    for (int m : shot_m) lane_of.emplace(m, (int)lane_of.size());
+    std::vector<int> launch_lane;
     std::vector<GroupEntry> host;
     std::vector<Launch> plan;
     size_t rounds = 0;
@@ -1833,7 +1860,10 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
             if (r >= ops[sh].size()) continue;
             const Op &o = ops[sh][r];
             if (o.is_pass && stream_has_group(o.key, o.a.w.iso != 0)) passes.push_back({sh, r});
-            else plan.push_back(Launch{false, {}, false, false, false, 0, 0, 0, (int)sh, (int)r, 0});
+            else {
+                plan.push_back(Launch{false, {}, false, false, false, 0, 0, 0, (int)sh, (int)r, 0});
+                launch_lane.push_back(lane_of[shot_m[sh]]);
+            }
         }
         std::vector<bool> done(passes.size(), false);
         for (size_t p = 0; p < passes.size(); ++p) {
@@ -1867,6 +1897,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
             // compete for the cache together
             L.ntl = stream_loads(lead.loads, resident, lead.key.T);
             plan.push_back(L);
+            launch_lane.push_back(lane_of[lead.key.M]);
         }
     }
     if (host.size() > max_entries) return FD_EWORKSPACE;
@@ -1874,8 +1905,22 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
         FDW_HIP(hipMemcpyAsync(dev_entries, host.data(), host.size() * sizeof(GroupEntry),
                                hipMemcpyHostToDevice, s));
     FDW_HIP(hipStreamSynchronize(s));
-    auto issue = [&](hipStream_t st) {
-        for (const Launch &L : plan) {
+    const int nl = (int)lane_of.size();
+    LaneSet lanes;
+    for (int l = 0; nl > 1 && l < nl; ++l) {
+        hipStream_t t = nullptr;
+        FDW_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        lanes.streams.push_back(t);
+    }
+    auto issue = [&](hipStream_t base) {
+        if (nl > 1) {
+            hipEvent_t fork = lanes.event();
+            FDW_HIP(hipEventRecord(fork, base));
+            for (hipStream_t t : lanes.streams) FDW_HIP(hipStreamWaitEvent(t, fork, 0));
+        }
+        for (size_t li = 0; li < plan.size(); ++li) {
+            const Launch &L = plan[li];
+            const hipStream_t st = nl > 1 ? lanes.streams[launch_lane[li]] : base;
             if (L.grouped) {
                 if (!launch_stream_grouped(L.key, L.iso, L.ntl, L.ps, dev_entries + L.off, L.n, L.total,
                                            L.grid, st))
@@ -1891,6 +1936,12 @@ int run_merged(std::vector<std::vector<Op>> &ops, GroupEntry *dev_entries, size_
                 }
             }
         }
+        if (nl > 1)
+            for (hipStream_t t : lanes.streams) {
+                hipEvent_t join = lanes.event();
+                FDW_HIP(hipEventRecord(join, t));
+                FDW_HIP(hipStreamWaitEvent(base, join, 0));
+            }
     };
     if (!graph) {
         issue(s);
@@ -1977,7 +2028,9 @@ extern "C" int fd_forward_batch(int nshots, fd_shot *shots, void *workspace, siz
             off += b;
             entries += entry_bound(sh, FD_OP_FORWARD);
         }
-        return run_merged(ops, (GroupEntry *)((char *)workspace + off), entries,
+        std::vector<int> shot_m(nshots);
+        for (int i = 0; i < nshots; ++i) shot_m[i] = jobs[i].c.d.M;
+        return run_merged(ops, shot_m, (GroupEntry *)((char *)workspace + off), entries,
                           (batch_flags & FD_BATCH_GRAPH) != 0, (hipStream_t)stream);
     });
 }
@@ -2007,7 +2060,9 @@ extern "C" int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, si
             off += b;
             entries += entry_bound(sh, FD_OP_GRADIENT);
         }
-        const int rc = run_merged(ops, (GroupEntry *)((char *)workspace + off), entries,
+        std::vector<int> shot_m(nshots);
+        for (int i = 0; i < nshots; ++i) shot_m[i] = jobs[i].c.d.M;
+        const int rc = run_merged(ops, shot_m, (GroupEntry *)((char *)workspace + off), entries,
                                   (batch_flags & FD_BATCH_GRAPH) != 0, (hipStream_t)stream);
         if (rc) return rc;
         for (int i = 0; i < nshots; ++i) shots[i].misfit = grad_misfit(jobs[i]);
