@@ -227,13 +227,26 @@ def oracle_baseline(cs, budget_s=20.0):
         oracle.forward(prob, amp=amp[:steps])
         return time.perf_counter() - t0
 
+    import ctypes
+
+    gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle is built with
+    cores = int(gomp.omp_get_max_threads())
     t3 = run(3) / 3.0
     steps = int(max(2, min(500, budget_s / max(t3, 1e-3))))
     t = run(steps)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(npts * steps / t / 1e9, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} of the {cs['nt']} steps of {cs['name']} at full size ({npts} points), FP64",
-            "seconds": round(t, 3)}
+    out = {"value": round(npts * steps / t / 1e9, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} of the {cs['nt']} steps of {cs['name']} at full size ({npts} points), FP64",
+           "seconds": round(t, 3)}
+    # the same loop nest on one core (a bounded sample of a few steps)
+    gomp.omp_set_num_threads(1)
+    try:
+        t1 = run(1)
+        steps1 = int(max(1, min(20, 0.3 * budget_s / max(t1, 1e-3))))
+        ts = run(steps1) if steps1 > 1 else t1
+    finally:
+        gomp.omp_set_num_threads(cores)
+    out["one_core"] = {"value": round(npts * steps1 / ts / 1e9, 4), "steps": steps1, "seconds": round(ts, 3)}
+    return out
 
 
 # Time-blocking study on the HBM-bound 512^3 grid of the so-16 workload: for
