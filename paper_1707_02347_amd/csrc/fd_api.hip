@@ -1828,7 +1828,7 @@ struct LaneSet {
     }
 };
 
-int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m,
+int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_lane,
                GroupEntry *dev_entries, size_t max_entries, bool graph, hipStream_t s)
 {
     struct Launch {
@@ -1842,13 +1842,14 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m
         int shot, idx;
         int grid;
     };
-    // Lanes: a grouped launch only holds shots of one space order, so the work
-    // of each space order is a chain independent of the others.  Each lane
-    // gets a stream of its own, forked from and joined back to the issuing
-    // stream, so that the launches of different orders overlap (one order's
-    // tail of workgroups leaves CUs that another's launch can fill).
+    // Lanes: shot_lane[i] names the lane of shot i (its space order); a
+    // grouped launch only holds shots of one lane, so each lane's work is a
+    // chain independent of the others.  Each lane gets a stream of its own,
+    // forked from and joined back to the issuing stream, so that the launches
+    // of different lanes overlap (one lane's tail of workgroups leaves CUs
+    // that another's launch can fill).
     std::map<int, int> lane_of;
-    for (int m : shot_m) lane_of.emplace(m, (int)lane_of.size());
+    for (int m : shot_lane) lane_of.emplace(m, (int)lane_of.size());
     std::vector<int> launch_lane;
     std::vector<GroupEntry> host;
     std::vector<Launch> plan;
@@ -1862,7 +1863,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m
             if (o.is_pass && stream_has_group(o.key, o.a.w.iso != 0)) passes.push_back({sh, r});
             else {
                 plan.push_back(Launch{false, {}, false, false, false, 0, 0, 0, (int)sh, (int)r, 0});
-                launch_lane.push_back(lane_of[shot_m[sh]]);
+                launch_lane.push_back(lane_of[shot_lane[sh]]);
             }
         }
         std::vector<bool> done(passes.size(), false);
@@ -1876,7 +1877,8 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m
                 const KernelKey &k = o.key;
                 if (done[q] || k.M != lead.key.M || k.T != lead.key.T || k.PY != lead.key.PY ||
                     k.NW != lead.key.NW || k.mode != lead.key.mode || (o.a.w.iso != 0) != L.iso ||
-                    o.loads != lead.loads || o.a.ps != lead.a.ps)
+                    o.loads != lead.loads || o.a.ps != lead.a.ps ||
+                    shot_lane[passes[q].first] != shot_lane[passes[p].first])
                     continue;
                 done[q] = true;
                 resident += resident_bytes(o.a, k.mode);
@@ -1897,7 +1899,7 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_m
             // compete for the cache together
             L.ntl = stream_loads(lead.loads, resident, lead.key.T);
             plan.push_back(L);
-            launch_lane.push_back(lane_of[lead.key.M]);
+            launch_lane.push_back(lane_of[shot_lane[passes[p].first]]);
         }
     }
     if (host.size() > max_entries) return FD_EWORKSPACE;
