@@ -161,3 +161,35 @@ def test_dense_receiver_plane_equals_untiled(off):
         out = gpu_fwd(cs, **o)
         assert torch.equal(out["rec"], base["rec"]), o
         assert torch.equal(out["u"], base["u"]), o
+
+
+def test_full_size_offgrid_headline_tiled_equals_untiled():
+    """256^3 so 8, 500 steps, source and 256 receivers between nodes, in the
+    launch configuration the benchmark times: the tiled sweep equals the
+    untiled one bit for bit (the untiled kernel is pinned to the oracle at
+    smaller sizes)."""
+    import bench
+
+    cs = bench.offgrid(dict(bench.workload("cfg2", device=DEV), rec=synth.receiver_line((256,) * 3, 256, depth=20)))
+    outs = []
+    for opt in (dict(variant=L.FD_VARIANT_NAIVE), bench.launch_options("cfg2")):
+        outs.append(api.forward(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
+                                sponge=cs["sponge"], vref=cs["vref"], **opt))
+    assert torch.equal(outs[0]["rec"], outs[1]["rec"])
+    assert torch.equal(outs[0]["u"], outs[1]["u"])
+    assert float(outs[1]["rec"].abs().max()) > 0
+
+
+def test_full_size_born_tiled_equals_untiled():
+    """Born modelling on the headline grid (256^3 so 8, 500 steps, 256
+    receivers) in the benchmark's launch configuration equals the untiled run."""
+    import bench
+
+    cs = bench.workload("cfg2", device=DEV)
+    rec = synth.receiver_line((256,) * 3, 256, depth=20)
+    dv = 0.05 * (synth.blob_velocity(cs["v"], amp=1.0, width_frac=1.0 / 16.0) - cs["v"])
+    outs = [api.born(cs["v"], cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], rec, dv,
+                     sponge=cs["sponge"], vref=cs["vref"], **opt)
+            for opt in (dict(variant=L.FD_VARIANT_NAIVE), bench.launch_options("cfg2"))]
+    assert torch.equal(outs[0], outs[1])
+    assert float(outs[1].abs().max()) > 0
