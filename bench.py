@@ -424,6 +424,9 @@ def main():
                     help="only the headline tiled sweep (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8"], default=None,
+                    help="only 20-step sweeps of one more workload, for profiling runs: cfg3 "
+                         "(512^3 so 16, tiled) or tblock-so8 (512^3 so 8, T = 1 then T = 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -441,6 +444,23 @@ def main():
         ms = _timed(lambda: y.copy_(x), 5, 2)[0]
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return 0
+    if args.kernel_only:
+        import synth
+
+        cs = workload("cfg3")
+        opts = [launch_options("cfg3")]
+        if args.kernel_only == "tblock-so8":
+            cs["so"] = 8
+            cs["dt"] = 0.8 * courant_max(8, 3) * 10.0 / 4500.0
+            cs["amp"] = torch.from_numpy(synth.ricker(cs["nt"], cs["dt"], 15.0)[:, None].copy()).to("cuda")
+            opts = list(TIME_BLOCKING[8])
+        for o in opts:
+            for _ in range(args.warmup + args.steps):
+                _sweep(cs, o, nt=20)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": args.kernel_only, "sweeps": args.warmup + args.steps, "steps": 20}),
+              flush=True)
         return 0
     cs = workload("cfg2")
     npts = int(np.prod(cs["v"].shape))
