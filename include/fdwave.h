@@ -30,6 +30,9 @@
  *   * sources are injected in the step producing u^{n+1}:
  *       u^{n+1}(s) += 2 dt^2 w[n][s] / (dt damp(s) + 2 m(s));
  *   * receivers record the new level on grid nodes: d[n][r] = u^{n+1}(r);
+ *   * a point between grid nodes acts through multilinear interpolation over
+ *     the nodes of its cell (fd_points.pos), which keeps the two rules above
+ *     as the single-node case and the adjoint an exact transpose;
  *   * sponge: damp(i) = sum_a d0_a (delta_a / L)^2 with delta_a the number of
  *     cells into the outer L-cell layer of axis a (0 in the interior and at the
  *     layer's inner edge) and d0_a = 1.5 ln(1000) / (vref L h_a)  [s/m^2];
@@ -51,8 +54,16 @@
  *
  * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL is
  * the default stream) and returns without waiting, except (i) the stability
- * check, which reads back max(v) (skip it with FD_FLAG_NO_CFL_CHECK), and
- * (ii) fd_gradient when `misfit` is non-NULL, which waits for the misfit.
+ * check, which reads back max(v) (skip it with FD_FLAG_NO_CFL_CHECK), (ii) the
+ * upload of the point tables in each call's set-up, which waits for its copies
+ * on `stream`, and (iii) fd_gradient when `misfit` is non-NULL, which waits for
+ * the misfit.  The batched entry points fork the work of each space order onto
+ * a stream of their own and join it back into `stream` before returning.
+ *
+ * Operations: fd_forward, fd_adjoint (its transpose), fd_gradient and fd_vjp
+ * (adjoint-state derivatives with respect to v), fd_born (the linearised
+ * forward map, fd_vjp's transpose), their batched forms for many shots, and
+ * fd_autotune (picks a kernel configuration for a grid).
  *
  * Errors: every entry point returns 0 (FD_OK) or a negative FD_E* code; no
  * C++ exception crosses the ABI.  On error nothing further is enqueued, but
