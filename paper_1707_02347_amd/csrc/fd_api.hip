@@ -1036,6 +1036,37 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
     }
 }
 
+// One step of fused Born modelling: background (sb, sources injected) and
+// perturbation (sp, receivers recorded) advance in one pass of kernel `k`
+// (mode kBornFused), each updated in place over its previous level.
+void born_fused_step(Ctx &c, State &sb, State &sp, int64_t step, const KernelKey &k)
+{
+    const Dims &d = c.d;
+    SweepArgs a = c.base;
+    a.step0 = (int)step;
+    a.u0 = sb.cur;
+    a.um = sb.prev;
+    a.o1 = sb.prev;
+    a.u0b = sp.cur;
+    a.umb = sp.prev;
+    a.o2 = sp.prev;
+    a.lx = (c.plan.key.T == 1 && k.PY == c.plan.key.PY && k.NW == c.plan.key.NW) ? c.plan.lx
+                                                                                 : default_lx(d, k);
+    const int ty = stream_core_rows(k), tz = stream_core_cols(k);
+    a.ntz = (d.nz + tz - 1) / tz;
+    a.nty = (d.ny + ty - 1) / ty;
+    a.ntx = (d.nx + a.lx - 1) / a.lx;
+    a.remap = c.plan.remap ? 1 : 0;
+    a.alt = c.plan.alt ? 1 : 0;
+    // two fields and their coefficient: u, u_prev, du, du_prev, q, s
+    a.ntl = stream_loads(c.plan.loads, 2.0 * resident_bytes(a, kPlain), 1) ? 1 : 0;
+    a.ps = stage_points(c, k, a) ? 1 : 0;
+    supertile(k, a);
+    c.ex.pass(k, a, c.plan.loads);
+    std::swap(sb.cur, sb.prev);
+    std::swap(sp.cur, sp.prev);
+}
+
 // Move the final pair (st.cur, st.prev) into the caller's (A, B); tmp is a
 // field distinct from A, B, st.cur and st.prev.
 void place_state(const State &st, float *A, float *B, float *tmp, int64_t N, hipStream_t s)
@@ -1369,16 +1400,30 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
         pb.bs = bs;
         State sb{c.L.fields[0], c.L.fields[1], {c.L.fields[2], c.L.fields[3], nullptr}, 2};
         State sp{c.L.fields[4], c.L.fields[5], {c.L.fields[6], c.L.fields[7], nullptr}, 2};
-        StepOpts fo, bo;
-        fo.mode = kSaveD2;
-        bo.mode = kBorn;
-        fo.dslot_first = bo.dslot_first = 0;
-        fo.ddir = bo.ddir = 0;
-        for (int64_t k = 0; k < c.nt; ++k) {
-            c.base = bg;
-            advance(c, sb, k, 1, fo);
-            c.base = pb;
-            advance(c, sp, k, 1, bo);
+        // one pass per step when a fused kernel for this order is compiled
+        // (32 B per point instead of 44), else two passes per step
+        const KernelKey fk = key_for(c.plan.key, 1, kBornFused, c.base.w.iso != 0);
+        const bool fused = c.plan.variant != FD_VARIANT_NAIVE && fk.mode == kBornFused &&
+                           stream_has(fk, c.base.w.iso != 0);
+        if (fused) {
+            SweepArgs fa = c.base;
+            fa.amp = src ? src->amp : nullptr;
+            fa.rec_out = rec_out;
+            fa.bs = bs;
+            c.base = fa;
+            for (int64_t k = 0; k < c.nt; ++k) born_fused_step(c, sb, sp, k, fk);
+        } else {
+            StepOpts fo, bo;
+            fo.mode = kSaveD2;
+            bo.mode = kBorn;
+            fo.dslot_first = bo.dslot_first = 0;
+            fo.ddir = bo.ddir = 0;
+            for (int64_t k = 0; k < c.nt; ++k) {
+                c.base = bg;
+                advance(c, sb, k, 1, fo);
+                c.base = pb;
+                advance(c, sp, k, 1, bo);
+            }
         }
         gather_traces(c, c.L.rec, nr, pb.rec.cnt, rec_out, 1.0f);
         record_last(c.plan);

@@ -78,6 +78,8 @@ struct SweepArgs {
     double *g;        // imaging accumulator (FP64, N)
     const float *bs;  // Born: scattering coefficient 2 dv / v (N); d2 slot dslot0 holds
                       // the background's second difference
+    const float *u0b; // fused Born: the perturbation's u^n and u^{n-1} (o2 receives
+    const float *umb; // its u^{n+1}, and may alias umb)
     // tiling of the launch
     int lx;           // planes per workgroup along x
     int ntz, nty, ntx;
@@ -109,7 +111,10 @@ constexpr bool points_stageable(int PY, int NW) { return NW < 16 && PY <= 4; }
 // the volume source s * d2 inside the division: (num + s d2) / (1 + eta), with
 // s = 2 dv / v and d2 the background's second difference at the same step
 // (single-step passes only).
-enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2, kBorn = 3 };
+// kBornFused: background (u0/um -> o1, sources injected) and perturbation
+// (u0b/umb -> o2, receivers recorded) of Born modelling in one pass, the
+// perturbation's source formed from the background's new level in registers.
+enum Mode { kPlain = 0, kSaveD2 = 1, kImaging = 2, kBorn = 3, kBornFused = 4 };
 
 // The damped update's division u = num / (1 + eta), taken only where eta != 0
 // (the sponge), as num times the hardware reciprocal of 1 + eta (v_rcp_f32,

@@ -116,6 +116,10 @@ struct StreamKernel {
     // cache policy of the loads each point needs once per step (u^{n-1}, q,
     // and the gradient fields)
     static constexpr int LP = NTL ? kStream : kKeep;
+    // kBornFused: background and perturbation in one pass (two fields, F = 2)
+    static constexpr bool FUSED = (MODE == kBornFused);
+    static_assert(!FUSED || T == 1, "fused Born passes are single-step");
+    static constexpr int F = FUSED ? 2 : 1;
     // PS: the chunk's point entries are staged in LDS (the host launches this
     // form only when every chunk's entries fit); otherwise the per-plane walk
     // reads the tables in memory.  Each form holds one walk only: both in one
@@ -163,7 +167,7 @@ struct StreamKernel {
     // reads next to its own (used only where they lie inside the level's
     // region) always stay inside the buffer; per-plane tables of the chunk.
     struct Smem {
-        float s0[2][G::L0H * G::L0W];
+        float s0[F][2][G::L0H * G::L0W];  // field f's level-0 plane (two parities)
         float s1[(T > 1) ? (T - 1) : 1][2][(T > 1) ? (G::RY + 2 * M) * G::RZ : 1];
         float px[G::SPAN];
         int ixb[G::SPAN], ixe[G::SPAN];  // per plane: source entries this tile may hold
@@ -186,6 +190,7 @@ struct StreamKernel {
     static constexpr bool IMG = (MODE == kImaging);
     static constexpr bool BORN = (MODE == kBorn);
     static_assert(!BORN || T == 1, "Born passes are single-step");
+
     struct Pre {
         float head[PY];
         float halo[G::HS];
@@ -197,7 +202,9 @@ struct StreamKernel {
         float d2[IMG ? T : 1][IMG ? PY : 1];
         // Born: the scattering coefficient and the background's second
         // difference at level 1's plane
-        float bs[BORN ? PY : 1], bd[BORN ? PY : 1];
+        float bs[(BORN || FUSED) ? PY : 1], bd[BORN ? PY : 1];
+        // fused Born: the perturbation field's head, halo and previous level
+        float head2[FUSED ? PY : 1], halo2[FUSED ? G::HS : 1], up2[FUSED ? PY : 1];
     };
 
     struct Thread {
@@ -345,9 +352,11 @@ struct StreamKernel {
         }
         // (the first barrier of the loop orders these writes before any read)
 
-        float qu[T][PY][QS];  // level t's queue of u^{t-1}: planes c_t - M .. c_t + M
+        // level t's queue of u^{t-1}: planes c_t - M .. c_t + M (the fused Born
+        // kernel keeps the perturbation's queue in entry T)
+        float qu[T + F - 1][PY][QS];
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+        for (int t = 0; t < T + F - 1; ++t)
 #pragma unroll
             for (int r = 0; r < PY; ++r)
 #pragma unroll
@@ -377,6 +386,11 @@ struct StreamKernel {
             const auto rh = plane_rsrc(a.u0, ph, a.sxy, (unsigned)ph < (unsigned)a.nx);
 #pragma unroll
             for (int r = 0; r < PY; ++r) qu[0][r][pjb<0>(j + 1)] = bload(rh, th.bo[r]);
+            if constexpr (FUSED) {
+                const auto rh2 = plane_rsrc(a.u0b, ph, a.sxy, (unsigned)ph < (unsigned)a.nx);
+#pragma unroll
+                for (int r = 0; r < PY; ++r) qu[T][r][pjb<0>(j + 1)] = bload(rh2, th.bo[r]);
+            }
         }
 
         Pre pf[NS];  // slot (i - istart) mod NS holds the loads of iteration i
@@ -459,11 +473,22 @@ struct StreamKernel {
             constexpr int COFF = (t == 1) ? M : 0;
             float *S;
             if constexpr (t == 1) {
-                S = sm.s0[par];
+                S = sm.s0[0][par];
 #pragma unroll
                 for (int s = 0; s < G::HS; ++s) {
                     int row, col;
                     if (halo_pos(threadIdx.x + s * G::NT, row, col)) S[row * G::L0W + col] = P.halo[s];
+                }
+                if constexpr (FUSED) {
+                    float *S2 = sm.s0[1][par];
+#pragma unroll
+                    for (int s = 0; s < G::HS; ++s) {
+                        int row, col;
+                        if (halo_pos(threadIdx.x + s * G::NT, row, col)) S2[row * G::L0W + col] = P.halo2[s];
+                    }
+#pragma unroll
+                    for (int r = 0; r < PY; ++r)
+                        S2[(th.wv * PY + r + M) * W + th.lane + COFF] = qu[T][r][pjb<PH>(M + 1)];
                 }
             } else {
                 S = sm.s1[t - 2][par];
@@ -534,6 +559,21 @@ struct StreamKernel {
         const auto rm = plane_rsrc(a.um, c1, a.sxy, l1);
 #pragma unroll
         for (int r = 0; r < PY; ++r) P.up1[r] = bload<LP>(rm, th.bo[r]);
+        if constexpr (FUSED) {
+            const auto rh2 = plane_rsrc(a.u0b, ph, a.sxy, (unsigned)ph < (unsigned)a.nx && i < th.iend);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) P.head2[r] = bload(rh2, th.bo[r]);
+            const auto rc2 = plane_rsrc(a.u0b, c1, a.sxy, l1);
+#pragma unroll
+            for (int s = 0; s < G::HS; ++s) P.halo2[s] = bload(rc2, th.hb[s]);
+            const auto rm2 = plane_rsrc(a.umb, c1, a.sxy, l1);
+            const auto rs = plane_rsrc(a.bs, c1, a.sxy, l1);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                P.up2[r] = bload<LP>(rm2, th.bo[r]);
+                P.bs[r] = bload<LP>(rs, th.bo[r]);
+            }
+        }
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int ct = plane(th, i - t * M);
@@ -594,8 +634,20 @@ struct StreamKernel {
         constexpr int W = (t == 1) ? G::L0W : G::RZ;
         constexpr int OFF = M;          // row offset (and, for t == 1, column offset)
         constexpr int COFF = (t == 1) ? M : 0;
+        if constexpr (FUSED) {
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                if constexpr (ROT) {
+                    qu[T][r][PH] = P.head2[r];
+                } else {
+#pragma unroll
+                    for (int j = 0; j + 1 < Q; ++j) qu[T][r][j] = qu[T][r][j + 1];
+                    qu[T][r][Q - 1] = P.head2[r];
+                }
+            }
+        }
         const float *S;
-        if constexpr (t == 1) S = sm.s0[par];
+        if constexpr (t == 1) S = sm.s0[0][par];
         else S = sm.s1[t - 2][par];
 
         // level t's region: owned region shrunk by M (t - 1)
@@ -603,6 +655,7 @@ struct StreamKernel {
         const bool xin = (unsigned)c < (unsigned)a.nx;
         const bool zreg = lane >= lo && lane < G::RZ - lo;
         float out[PY];
+        float out2[FUSED ? PY : 1];  // fused Born: the perturbation's new level
         if (needed(a, th, t, c)) {
             const int tj = c - th.cbase;  // index into the per-plane tables
             const float pxv = sm.px[tj];
@@ -697,6 +750,54 @@ struct StreamKernel {
                     }
                 }
             }
+            if constexpr (FUSED) {
+                // the perturbation: the same update of its own field, plus the
+                // Born source s d2 inside the division, d2 the background's
+                // second difference at this point (after its injection)
+                const float *S2 = sm.s0[1][par];
+                float colv[PY + 2 * M];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    colv[j] = S2[(wv * PY - M + j + OFF) * W + lane + COFF];
+                    colv[M + PY + j] = S2[(wv * PY + PY + j + OFF) * W + lane + COFF];
+                }
+#pragma unroll
+                for (int r = 0; r < PY; ++r) colv[M + r] = qu[T][r][pj<PH>(M)];
+#pragma unroll
+                for (int r = 0; r < PY; ++r) {
+                    const int rr = wv * PY + r;
+                    const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
+                    const float d2 = fmaf(-2.0f, qu[0][r][pj<PH>(M)], out[r]) + P.up1[r];
+                    const float uc = qu[T][r][pj<PH>(M)];
+                    const float *row = S2 + (rr + OFF) * W + lane + COFF;
+                    float lap = 0.0f;
+#pragma unroll
+                    for (int k = 1; k <= M; ++k) {
+                        const float xs = qu[T][r][pj<PH>(M - k)] + qu[T][r][pj<PH>(M + k)];
+                        const float ys = colv[M + r - k] + colv[M + r + k];
+                        const float zs = row[-k] + row[k];
+                        if constexpr (ISO) {
+                            lap = fmaf(a.w.wx[k - 1], fmaf(a.w.cc, uc, (xs + ys) + zs), lap);
+                        } else {
+                            lap = fmaf(a.w.wx[k - 1], fmaf(-2.0f, uc, xs), lap);
+                            lap = fmaf(a.w.wy[k - 1], fmaf(-2.0f, uc, ys), lap);
+                            lap = fmaf(a.w.wz[k - 1], fmaf(-2.0f, uc, zs), lap);
+                        }
+                    }
+                    const float qv = P.q[0][r];
+                    const float eta = qv * (pxv + th.pyz[r]);
+                    float num = fmaf(qv, lap, fmaf(eta - 1.0f, P.up2[r], 2.0f * uc));
+                    num = fmaf(P.bs[r], d2, num);
+                    out2[r] = active ? damped(num, eta) : 0.0f;
+                }
+            }
+            // the field receivers sample: the perturbation in the fused Born pass
+            float recv[PY];
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+                if constexpr (FUSED) recv[r] = out2[r];
+                else recv[r] = out[r];
+            }
             if (c >= th.x0 && c < th.xend) {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.rxb[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.rxe[tj]);
@@ -722,7 +823,7 @@ struct StreamKernel {
 #pragma unroll
                             for (int r = 0; r < PY; ++r) {
                                 const float o = __int_as_float(
-                                    __builtin_amdgcn_ds_bpermute(lk << 2, __float_as_int(out[r])));
+                                    __builtin_amdgcn_ds_bpermute(lk << 2, __float_as_int(recv[r])));
                                 if (r == rk) v = o;
                             }
                             if (code >= 0 && (code >> 16) == sw) sm.rval[t - 1][k] = v * rs;
@@ -733,7 +834,7 @@ struct StreamKernel {
                             const int dst = ent ? j : a.rec.id[j];
 #pragma unroll
                             for (int r = 0; r < PY; ++r)
-                                if (th.core[r] && th.bo[r] == p) orow[dst] = out[r] * rs;
+                                if (th.core[r] && th.bo[r] == p) orow[dst] = recv[r] * rs;
                         }
                     }
                 }
@@ -741,6 +842,10 @@ struct StreamKernel {
         } else {
 #pragma unroll
             for (int r = 0; r < PY; ++r) out[r] = 0.0f;
+            if constexpr (FUSED) {
+#pragma unroll
+                for (int r = 0; r < PY; ++r) out2[r] = 0.0f;
+            }
         }
         // gradient support (outside the branch above, so that every memory
         // operation of the iteration is issued unconditionally; own planes are
@@ -780,6 +885,11 @@ struct StreamKernel {
             const auto r1 = plane_rsrc(a.o1, c, a.sxy, outp);
 #pragma unroll
             for (int r = 0; r < PY; ++r) bstore<kStream>(r1, out_off(th, r), out[r]);
+            if constexpr (FUSED) {
+                const auto r2 = plane_rsrc(a.o2, c, a.sxy, outp);
+#pragma unroll
+                for (int r = 0; r < PY; ++r) bstore<kStream>(r2, out_off(th, r), out2[r]);
+            }
             if constexpr (T >= 2) {
                 const auto r2 = plane_rsrc(a.o2, c, a.sxy, outp);
 #pragma unroll

@@ -16,18 +16,20 @@
     X(1, 1, 4, 8, 1, FDW_AG) X(1, 1, 4, 8, 2, FDW_AG) X(1, 2, 4, 8, 0, FDW_AG)             \
     X(1, 2, 2, 16, 0, FDW_AG) X(1, 3, 4, 8, 0, FDW_G) X(1, 3, 2, 16, 0, FDW_G)              \
     X(1, 4, 4, 8, 0, 0) X(1, 4, 2, 16, 0, 0) X(1, 2, 4, 8, 1, FDW_G) X(1, 2, 4, 8, 2, FDW_G)             \
-    X(1, 1, 4, 8, 3, FDW_A)
+    X(1, 1, 4, 8, 3, FDW_A) X(1, 1, 4, 8, 4, FDW_A)
 
 #define FDW_CONFIGS_M2(X)                                                                  \
     X(2, 1, 8, 4, 0, FDW_AG) X(2, 1, 4, 4, 0, FDW_AG) X(2, 1, 4, 8, 0, FDW_AG)             \
     X(2, 1, 16, 2, 0, 0) X(2, 1, 8, 4, 1, FDW_AG) X(2, 1, 8, 4, 2, FDW_AG)                 \
     X(2, 1, 4, 8, 1, FDW_AG) X(2, 1, 4, 8, 2, FDW_AG) X(2, 2, 4, 8, 0, FDW_AG)             \
     X(2, 2, 2, 16, 0, FDW_AG) X(2, 3, 4, 8, 0, FDW_G) X(2, 3, 2, 16, 0, FDW_G)              \
-    X(2, 4, 2, 16, 0, 0) X(2, 2, 4, 8, 1, FDW_G) X(2, 2, 4, 8, 2, FDW_G) X(2, 1, 4, 8, 3, FDW_A)
+    X(2, 4, 2, 16, 0, 0) X(2, 2, 4, 8, 1, FDW_G) X(2, 2, 4, 8, 2, FDW_G) X(2, 1, 4, 8, 3, FDW_A)    \
+    X(2, 1, 4, 8, 4, FDW_A)
 
 #define FDW_CONFIGS_M3(X)                                                                  \
     X(3, 1, 8, 4, 0, FDW_AG) X(3, 1, 8, 4, 1, FDW_AG) X(3, 1, 8, 4, 2, FDW_AG)             \
-    X(3, 1, 4, 8, 0, FDW_AG) X(3, 1, 4, 8, 1, FDW_AG) X(3, 1, 4, 8, 2, FDW_AG) X(3, 1, 4, 8, 3, FDW_A)
+    X(3, 1, 4, 8, 0, FDW_AG) X(3, 1, 4, 8, 1, FDW_AG) X(3, 1, 4, 8, 2, FDW_AG) X(3, 1, 4, 8, 3, FDW_A)  \
+    X(3, 1, 4, 8, 4, FDW_A)
 #define FDW_CONFIGS_M5(X)                                                                  \
     X(5, 1, 8, 4, 0, FDW_AG) X(5, 1, 8, 4, 1, FDW_AG) X(5, 1, 8, 4, 2, FDW_AG)             \
     X(5, 1, 4, 4, 0, FDW_AG) X(5, 1, 4, 4, 1, FDW_AG) X(5, 1, 4, 4, 2, FDW_AG) X(5, 1, 4, 4, 3, FDW_A)
@@ -45,7 +47,7 @@
     X(4, 1, 4, 8, 2, FDW_AG) X(4, 2, 4, 8, 0, FDW_A) X(4, 2, 2, 16, 0, FDW_AG)            \
     X(4, 3, 4, 8, 0, 0) X(4, 3, 2, 16, 0, 0)                      \
     X(4, 2, 4, 8, 1, FDW_G) X(4, 2, 4, 8, 2, FDW_G) X(4, 2, 2, 16, 1, FDW_G)              \
-    X(4, 2, 2, 16, 2, 0) X(4, 1, 4, 8, 3, FDW_A)
+    X(4, 2, 2, 16, 2, 0) X(4, 1, 4, 8, 3, FDW_A) X(4, 1, 4, 8, 4, FDW_A)
 
 #define FDW_CONFIGS_M8(X)                                                                  \
     X(8, 1, 8, 4, 0, FDW_AG) X(8, 1, 4, 4, 0, FDW_AG) X(8, 1, 8, 2, 0, 0)                  \

@@ -1,6 +1,8 @@
 """Born (linearised) modelling on the GPU: traces against the FP64 oracle
-(rel-L2 1e-5), every kernel configuration bit-identical to the untiled one,
-and the FP32 dot test against the vector-Jacobian product (its transpose)."""
+(rel-L2 1e-5), every kernel configuration bit-identical to the untiled one
+(the tiled runs take the fused one-pass kernel for space orders up to 8 and
+two passes per step for so 16), and the FP32 dot test against the
+vector-Jacobian product (its transpose)."""
 import numpy as np
 import pytest
 import torch
@@ -32,7 +34,7 @@ def gpu_born(cs, dv, **opt):
                     vref=cs["vref"], **opt)
 
 
-@pytest.mark.parametrize("so,offgrid", [(4, False), (8, False), (8, True)])
+@pytest.mark.parametrize("so,offgrid", [(4, False), (8, False), (8, True), (16, False)])
 def test_born_matches_oracle_and_configs_agree(so, offgrid):
     cs, dv = born_case(so=so, offgrid=offgrid)
     prob = oracle.Problem(cs["v"].numpy().astype(np.float64), cs["h"], cs["so"], cs["nt"], cs["dt"],
