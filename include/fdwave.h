@@ -250,9 +250,10 @@ int fd_vjp(const fd_grid *grid, const fd_time *time, const float *v, const fd_po
  * respect to m = 1/v^2 (paper Sec. 6.3.1 update; dm = -2 dv / v^3) gives the
  * perturbation wavefield the same recurrence driven by the volume source
  * A^{-1} (-2 dm (u^k - 2u^{k-1} + u^{k-2})), u the background wavefield; each step
- * advances the background (saving its second difference) and then the
- * perturbation, whose update folds the source in as (num + s d2) / (1 + eta),
- * s = 2 dv / v.  fd_vjp is its transpose.
+ * advances the background and the perturbation, whose update folds the source
+ * in as (num + s d2) / (1 + eta), s = 2 dv / v, d2 the background's new second
+ * difference: in one pass over both fields for space orders up to 8 (tiled
+ * variants), else in two (the first saving d2).  fd_vjp is its transpose.
  *   dv       DEVICE [N] FP32 velocity perturbation (m/s).
  *   src->amp DEVICE [nt][ns] source wavelet of the background.
  *   rec_out  DEVICE [nt][nr] perturbed traces (may be NULL if nr == 0).
