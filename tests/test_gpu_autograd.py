@@ -101,3 +101,42 @@ def test_autograd_velocity_gradient_finite_difference():
     an = float((vd.grad.double() * dv.double()).sum())
     print(f"velocity FD {fd:.6e} vs adjoint {an:.6e}")
     assert abs(fd - an) <= 1e-2 * abs(an)
+
+
+def _jvp(f, x, t):
+    import torch.autograd.forward_ad as fwAD
+
+    with fwAD.dual_level():
+        out = fwAD.unpack_dual(f(fwAD.make_dual(x, t)))
+        return out.primal, out.tangent
+
+
+def test_forward_mode_velocity_tangent_is_born_modelling():
+    """Forward mode (dual tensors) along dv equals fd_born, matches the oracle's
+    Born traces, and pairs with the reverse-mode gradient: <J dv, y> = <dv, J^T y>."""
+    v, w, g, _ = setup()
+    vd = v.to(DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    dv = (synth.smooth_velocity(tuple(v.shape), seed=31, sigma=3.0) - 3000.0).to(DEV)
+    d, dd = _jvp(lambda vv: fd_model(vv, wd, g), vd, dv)
+    born = api.born(vd, g.h, g.space_order, g.nt, g.dt, g.src_idx, wd, g.rec_idx, dv, sponge=g.sponge, vref=g.vref)
+    assert torch.equal(dd, born)
+    prob = oracle.Problem(v.numpy().astype(np.float64), g.h, g.space_order, g.nt, g.dt, g.sponge, g.vref,
+                          g.src_idx, g.rec_idx)
+    ref = oracle.born(prob, w.astype(np.float64), dv.cpu().numpy().astype(np.float64))
+    assert np.linalg.norm(dd.cpu().numpy() - ref) <= 1e-5 * np.linalg.norm(ref)
+    y = torch.randn_like(d)
+    vg = vd.clone().requires_grad_(True)
+    (gv,) = torch.autograd.grad((fd_model(vg, wd, g) * y).sum(), vg)
+    lhs, rhs = float((dd.double() * y.double()).sum()), float((dv.double() * gv.double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_forward_mode_wavelet_tangent_is_the_forward_sweep():
+    v, w, g, _ = setup()
+    vd = v.to(DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    wt = torch.from_numpy(np.ascontiguousarray(w[::-1])).to(DEV)
+    _, dd = _jvp(lambda ww: fd_model(vd, ww, g), wd, wt)
+    ref = api.forward(vd, g.h, g.space_order, g.nt, g.dt, g.src_idx, wt, g.rec_idx, sponge=g.sponge, vref=g.vref)
+    assert torch.equal(dd, ref["rec"])
