@@ -71,7 +71,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field,
 // kStream (non-temporal) for data touched once per step.  Non-temporal stores
 // of the new field are faster at every size measured; non-temporal loads of
 // u^{n-1} and q only when the fields do not fit the Infinity Cache (they keep
-// q from staying there for the next step).
+// q from staying there for the next step).  The saved second differences are
+// read exactly once and always load non-temporally (256^3 gradient: 4.29 ->
+// 4.57 per second, the wavefields and the image stay in the cache).
 constexpr int kKeep = 0;
 constexpr int kStream = 2;
 
@@ -587,7 +589,7 @@ struct StreamKernel {
 #pragma unroll
             for (int r = 0; r < PY; ++r) {
                 P.bs[r] = bload<LP>(rs, th.bo[r]);
-                P.bd[r] = bload<LP>(rd, th.bo[r]);
+                P.bd[r] = bload<kStream>(rd, th.bo[r]);
             }
         }
         if constexpr (IMG) {
@@ -606,7 +608,7 @@ struct StreamKernel {
                                   (int64_t)(ot ? ct : 0) * a.sxy;
                 const auto rd = span_rsrc(dp, a.sxy * 4, ot);
 #pragma unroll
-                for (int r = 0; r < PY; ++r) P.d2[t - 1][r] = bload<LP>(rd, out_off(th, r));
+                for (int r = 0; r < PY; ++r) P.d2[t - 1][r] = bload<kStream>(rd, out_off(th, r));
             }
         }
     }
