@@ -62,8 +62,9 @@
  *
  * Operations: fd_forward, fd_adjoint (its transpose), fd_gradient and fd_vjp
  * (adjoint-state derivatives with respect to v), fd_born (the linearised
- * forward map, fd_vjp's transpose), their batched forms for many shots, and
- * fd_autotune (picks a kernel configuration for a grid).
+ * forward map, fd_vjp's transpose), their batched forms for many shots,
+ * fd_autotune (picks a kernel configuration for a grid) and fd_gradient_storage
+ * (picks a gradient's checkpoint interval for a memory budget).
  *
  * Errors: every entry point returns 0 (FD_OK) or a negative FD_E* code; no
  * C++ exception crosses the ABI.  On error nothing further is enqueued, but
@@ -178,6 +179,26 @@ typedef struct fd_options {
  */
 size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_points *src,
                          const fd_points *rec, const fd_options *opts, int op);
+
+/*
+ * Storage scheme of a gradient (op FD_OP_GRADIENT or FD_OP_VJP) for a memory
+ * budget: the paper's choice between a saved (full) and a buffered time
+ * dimension (Sec. 6.3.2), here between keeping every second difference and
+ * checkpointing with recomputation.  Sets inout->ckpt_every (other fields are
+ * kept) to
+ *   nt, the whole time axis stored (no recomputation: two sweeps per step
+ *       instead of three), when fd_workspace_size for it is <= budget; else
+ *   the interval with the smallest workspace (every interval below nt
+ *       recomputes the same nt steps, so the smallest footprint costs no time).
+ * *ws_bytes (may be NULL) receives fd_workspace_size for the chosen interval.
+ * Host-only: no device call, no allocation.  src/rec as in fd_workspace_size.
+ * Returns FD_OK; FD_EWORKSPACE if even the smallest workspace exceeds budget
+ * (*inout and *ws_bytes are still set to it); FD_EINVAL on a bad descriptor,
+ * op, nt < 1 or inout == NULL.
+ */
+int fd_gradient_storage(const fd_grid *grid, const fd_time *time, const fd_points *src,
+                        const fd_points *rec, int op, size_t budget, fd_options *inout,
+                        size_t *ws_bytes);
 
 /*
  * Forward sweep (Sec. 6.3.1 update, nt steps).

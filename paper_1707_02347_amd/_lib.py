@@ -108,6 +108,9 @@ _lib = None
 SYMBOLS = {
     "fd_workspace_size": (C.c_size_t, [C.POINTER(fd_grid), C.POINTER(fd_time), C.POINTER(fd_points),
                                        C.POINTER(fd_points), C.POINTER(fd_options), C.c_int]),
+    "fd_gradient_storage": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.POINTER(fd_points),
+                                      C.POINTER(fd_points), C.c_int, C.c_size_t, C.POINTER(fd_options),
+                                      C.POINTER(C.c_size_t)]),
     "fd_forward": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.POINTER(fd_points),
                              C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                              C.POINTER(fd_options), C.c_void_p]),
@@ -164,6 +167,10 @@ def _check(rc: int, where: str):
 # ------------------------------------------------------------------ thin mirrors of the C ABI
 def fd_workspace_size(grid, time, src, rec, opts, op):
     return load().fd_workspace_size(grid, time, src, rec, opts, op)
+
+
+def fd_gradient_storage(grid, time, src, rec, op, budget, inout, ws_bytes):
+    return load().fd_gradient_storage(grid, time, src, rec, op, budget, inout, ws_bytes)
 
 
 def fd_forward(grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts, stream):

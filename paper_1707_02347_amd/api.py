@@ -31,6 +31,27 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _opts_storage(variant, tile, tblock, ckpt_every, flags, grid, tm, src, rec, op, mem_budget, device):
+    """Options of a gradient-type call.  ckpt_every="auto" lets fd_gradient_storage
+    choose between storing the whole time axis and checkpointing, for mem_budget
+    bytes of workspace (default: 80 % of the device's free memory)."""
+    if ckpt_every != "auto":
+        if mem_budget is not None:
+            raise ValueError("mem_budget applies to ckpt_every='auto' only")
+        return _opts(variant, tile, tblock, ckpt_every, flags)
+    o = _opts(variant, tile, tblock, 0, flags)
+    budget = mem_budget
+    if budget is None:
+        budget = int(0.8 * torch.cuda.mem_get_info(device)[0])
+    need = C.c_size_t(0)
+    rc = L.fd_gradient_storage(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), op, int(budget),
+                               C.byref(o), C.byref(need))
+    if rc == L.FD_EWORKSPACE and mem_budget is None:
+        rc = L.FD_OK  # no explicit budget: try the smallest footprint anyway
+    L._check(rc, "fd_gradient_storage")
+    return o
+
+
 def forward(v, h, so, nt, dt, src_idx=None, src_amp=None, rec_idx=None, u0=None, um1=None,
             sponge=0, vref=1500.0, variant=0, tile=(0, 0, 0), tblock=0, flags=0):
     """Forward sweep; returns dict(rec=[nt][nr], u=u^nt, u_prev=u^{nt-1})."""
@@ -83,8 +104,10 @@ def adjoint(v, h, so, nt, dt, src_idx, rec_idx, rec_amp, sponge=0, vref=1500.0, 
 
 
 def gradient(v, h, so, nt, dt, src_idx, src_amp, rec_idx, d_obs, sponge=0, vref=1500.0, variant=0,
-             tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0):
-    """Least-squares misfit and dJ/dv (checkpointed adjoint state); returns (J, grad_v, residual)."""
+             tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0, mem_budget=None):
+    """Least-squares misfit and dJ/dv (adjoint state); returns (J, grad_v, residual).
+    ckpt_every: checkpoint interval (0 = 50, >= nt = whole time axis stored, "auto" =
+    chosen for mem_budget bytes of workspace)."""
     v = _dev_f32(v, "v")
     shape = tuple(v.shape)
     nd = len(shape)
@@ -92,7 +115,8 @@ def gradient(v, h, so, nt, dt, src_idx, src_amp, rec_idx, d_obs, sponge=0, vref=
     tm = L.make_time(nt, dt)
     src = L.Points(src_idx, _dev_f32(src_amp, "src_amp"), nd)
     rec = L.Points(rec_idx, _dev_f32(d_obs, "d_obs"), nd)
-    o = _opts(variant, tile, tblock, ckpt_every, flags)
+    o = _opts_storage(variant, tile, tblock, ckpt_every, flags, grid, tm, src, rec, L.FD_OP_GRADIENT, mem_budget,
+                      v.device)
     gv = torch.zeros(shape, dtype=torch.float32, device=v.device)
     res = torch.zeros((int(nt), rec.n), dtype=torch.float32, device=v.device)
     J = C.c_double(0.0)
@@ -107,8 +131,8 @@ def gradient(v, h, so, nt, dt, src_idx, src_amp, rec_idx, d_obs, sponge=0, vref=
 
 
 def vjp(v, h, so, nt, dt, src_idx, src_amp, rec_idx, y, sponge=0, vref=1500.0, variant=0,
-        tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0):
-    """(dd/dv)^T y for trace cotangent y [nt][nr]."""
+        tile=(0, 0, 0), tblock=0, ckpt_every=0, flags=0, mem_budget=None):
+    """(dd/dv)^T y for trace cotangent y [nt][nr]; ckpt_every as in gradient()."""
     v = _dev_f32(v, "v")
     shape = tuple(v.shape)
     nd = len(shape)
@@ -116,7 +140,8 @@ def vjp(v, h, so, nt, dt, src_idx, src_amp, rec_idx, y, sponge=0, vref=1500.0, v
     tm = L.make_time(nt, dt)
     src = L.Points(src_idx, _dev_f32(src_amp, "src_amp"), nd)
     rec = L.Points(rec_idx, _dev_f32(y, "y"), nd)
-    o = _opts(variant, tile, tblock, ckpt_every, flags)
+    o = _opts_storage(variant, tile, tblock, ckpt_every, flags, grid, tm, src, rec, L.FD_OP_VJP, mem_budget,
+                      v.device)
     gv = torch.zeros(shape, dtype=torch.float32, device=v.device)
     nbytes = L.fd_workspace_size(C.byref(grid), C.byref(tm), C.byref(src.s), C.byref(rec.s), C.byref(o),
                                  L.FD_OP_VJP)

@@ -3,9 +3,10 @@
 ``FdModel.apply(v, wavelet, geom)`` runs the forward sweep of libfdwave.so.
 Reverse mode (backward) returns
   * dL/dv through the library's checkpointed adjoint-state computation
-    (fd_vjp: forward checkpoints every ``geom.ckpt_every`` steps, segment
-    recomputation, adjoint sweep, zero-lag imaging condition accumulated in
-    FP64, dL/dm -> dL/dv = dL/dm * (-2 / v^3));
+    (fd_vjp: forward checkpoints every ``geom.ckpt_every`` steps and segment
+    recomputation, or the whole time axis stored, or ``"auto"``: the library
+    picks one for the device's free memory; adjoint sweep, zero-lag imaging
+    condition accumulated in FP64, dL/dm -> dL/dv = dL/dm * (-2 / v^3));
   * dL/dwavelet = F^T (dL/dd), the adjoint sweep read at the sources
     (fd_adjoint), since the traces are linear in the wavelet.
 Forward mode (jvp, with ``torch.autograd.forward_ad`` dual tensors) returns
@@ -35,7 +36,7 @@ class Geometry:
     sponge: int = 0
     vref: float = 1500.0
     options: dict = field(default_factory=dict)
-    ckpt_every: int = 0
+    ckpt_every: int | str = 0
 
 
 class FdModel(torch.autograd.Function):

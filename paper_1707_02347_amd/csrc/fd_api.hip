@@ -1290,6 +1290,42 @@ size_t fd_workspace_size(const fd_grid *grid, const fd_time *time, const fd_poin
     return L.bytes;
 }
 
+int fd_gradient_storage(const fd_grid *grid, const fd_time *time, const fd_points *src,
+                        const fd_points *rec, int op, size_t budget, fd_options *inout,
+                        size_t *ws_bytes)
+{
+    return guarded([&]() -> int {
+        Dims d;
+        if (!inout || make_dims(grid, d) || !time || time->nt < 1 || time->nt > INT32_MAX)
+            return FD_EINVAL;
+        if (op != FD_OP_GRADIENT && op != FD_OP_VJP) return FD_EINVAL;
+        if ((src && src->n < 0) || (rec && rec->n < 0)) return FD_EINVAL;
+        const int64_t nt = time->nt;
+        const PtsSpec S = spec_of(d, src), R = spec_of(d, rec);
+        auto bytes_at = [&](int64_t K) {
+            return layout(nullptr, d, nt, S, R, op, fields_needed(op), (int)K).bytes;
+        };
+        // The saved time dimension: one checkpoint, every second difference kept,
+        // no recomputation (two sweeps per step instead of three).
+        int64_t best = nt;
+        size_t need = bytes_at(nt);
+        if (need > budget) {
+            // Every interval below nt recomputes the same nt steps, so the one
+            // with the smallest footprint (about sqrt(2 nt)) costs nothing extra.
+            for (int64_t K = 1; K < nt; ++K) {
+                const size_t b = bytes_at(K);
+                if (b < need) {
+                    need = b;
+                    best = K;
+                }
+            }
+        }
+        inout->ckpt_every = (int32_t)best;
+        if (ws_bytes) *ws_bytes = need;
+        return need <= budget ? FD_OK : FD_EWORKSPACE;
+    });
+}
+
 int fd_forward(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
                const fd_points *rec, float *rec_out, float *u_state, void *workspace,
                size_t ws_bytes, const fd_options *opts, void *stream)

@@ -71,6 +71,62 @@ def test_checkpoint_interval_sets_gradient_workspace():
     assert abs((a - b) - ((40 + 10) - (8 + 50)) * N4) < 64 * 1024
 
 
+def _storage(g, t, budget, op=None, opts=None, src=None, rec=None):
+    o = opts if opts is not None else L.make_options()
+    need = C.c_size_t(0)
+    rc = L.fd_gradient_storage(C.byref(g), C.byref(t), None if src is None else C.byref(src.s),
+                               None if rec is None else C.byref(rec.s),
+                               L.FD_OP_GRADIENT if op is None else op, budget, C.byref(o), C.byref(need))
+    return rc, o, need.value
+
+
+@pytest.mark.parametrize("nt", [1, 2, 7, 200])
+def test_gradient_storage_picks_full_axis_or_smallest_checkpoints(nt):
+    g, t = _grid(), L.make_time(nt, 1e-3)
+    rec = L.Points(np.array([[3, 4, 5], [10, 11, 12]], np.int32), None, 3)
+
+    def size(k, op=L.FD_OP_GRADIENT):
+        o = L.make_options(ckpt_every=k)
+        return L.fd_workspace_size(C.byref(g), C.byref(t), None, C.byref(rec.s), C.byref(o), op)
+
+    full = size(nt)
+    # a budget that holds the whole time axis: every second difference is kept
+    for budget in (full, 10 * full):
+        rc, o, need = _storage(g, t, budget, rec=rec)
+        assert (rc, o.ckpt_every, need) == (L.FD_OK, nt, full)
+    # one byte less: the interval with the smallest workspace, found by brute force
+    sizes = {k: size(k) for k in range(1, nt + 1)}
+    kmin = min(sizes, key=lambda k: (sizes[k], k))
+    rc, o, need = _storage(g, t, full - 1, rec=rec)
+    assert o.ckpt_every == kmin and need == sizes[kmin]
+    assert rc == (L.FD_OK if sizes[kmin] <= full - 1 else L.FD_EWORKSPACE)
+    if nt == 200:
+        assert kmin == 20  # fields 2 ceil(nt/k) + k are fewest at k = sqrt(2 nt)
+    # nothing fits: the smallest is still reported
+    rc, o, need = _storage(g, t, 1000, rec=rec)
+    assert (rc, o.ckpt_every, need) == (L.FD_EWORKSPACE, kmin, sizes[kmin])
+    # the vector-Jacobian product sizes alike
+    rc, o, need = _storage(g, t, 10 * full, op=L.FD_OP_VJP, rec=rec)
+    assert (rc, o.ckpt_every, need) == (L.FD_OK, nt, size(nt, L.FD_OP_VJP))
+
+
+def test_gradient_storage_keeps_other_options_and_validates():
+    g, t = _grid(), L.make_time(50, 1e-3)
+    o = L.make_options(variant=L.FD_VARIANT_STREAM, tile=(16, 32, 4), tblock=1, ckpt_every=9,
+                       flags=L.FD_FLAG_LOADS_KEEP)
+    rc, o, _ = _storage(g, t, 1 << 40, opts=o)
+    assert rc == L.FD_OK
+    assert (o.variant, tuple(o.tile), o.tblock, o.ckpt_every, o.flags) == (
+        L.FD_VARIANT_STREAM, (16, 32, 4), 1, 50, L.FD_FLAG_LOADS_KEEP)
+    assert _storage(g, t, 1 << 40, op=L.FD_OP_FORWARD)[0] == L.FD_EINVAL
+    assert _storage(g, L.make_time(0, 1e-3), 1 << 40)[0] == L.FD_EINVAL
+    bad = _grid()
+    bad.space_order = 7
+    assert _storage(bad, t, 1 << 40)[0] == L.FD_EINVAL
+    assert L.fd_gradient_storage(C.byref(g), C.byref(t), None, None, L.FD_OP_GRADIENT, 1 << 40, None,
+                                 None) == L.FD_EINVAL
+
+
 def _call_forward(grid, time, src=None, rec=None, ws=None, ws_bytes=0, opts=None):
     src = src or L.Points(None, None, grid.ndim)
     rec = rec or L.Points(None, None, grid.ndim)

@@ -480,3 +480,26 @@ def test_full_storage_gradient_equals_checkpointed(opt):
     Jc, gc, rc = api.gradient(*args, torch.from_numpy(d_obs).to(DEV), ckpt_every=13, **kw)
     assert Jf == Jc and torch.equal(gf, gc) and torch.equal(rf, rc)
     assert torch.equal(api.vjp(*args, rc, ckpt_every=cs["nt"], **kw), api.vjp(*args, rc, ckpt_every=13, **kw))
+
+
+def test_auto_storage_follows_the_budget():
+    """ckpt_every="auto": a budget that holds the whole time axis stores it, a
+    smaller one checkpoints at the interval fd_gradient_storage reports; both
+    give the fixed-interval results bit for bit."""
+    cs, d_obs = gradient_case()
+    args = (cs["v"].to(DEV), cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"],
+            torch.from_numpy(cs["amp"]).to(DEV), cs["rec"])
+    kw = dict(sponge=cs["sponge"], vref=cs["vref"], variant=L.FD_VARIANT_STREAM)
+    d = torch.from_numpy(d_obs).to(DEV)
+    J0, g0, r0 = api.gradient(*args, d, ckpt_every=cs["nt"], **kw)
+    grid = L.make_grid(cs["shape"], cs["h"], cs["so"], cs["sponge"], cs["vref"])
+    tm = L.make_time(cs["nt"], cs["dt"])
+    rec = L.Points(cs["rec"], None, len(cs["shape"]))
+    full = L.fd_workspace_size(C.byref(grid), C.byref(tm), None, C.byref(rec.s),
+                               C.byref(L.make_options(ckpt_every=cs["nt"])), L.FD_OP_GRADIENT)
+    for budget in (None, full, full - 1):
+        J, g, r = api.gradient(*args, d, ckpt_every="auto", mem_budget=budget, **kw)
+        assert J == J0 and torch.equal(g, g0) and torch.equal(r, r0), budget
+    with pytest.raises(L.FdError):
+        api.gradient(*args, d, ckpt_every="auto", mem_budget=4096, **kw)
+    assert torch.equal(api.vjp(*args, r0, ckpt_every="auto", **kw), api.vjp(*args, r0, ckpt_every=13, **kw))
