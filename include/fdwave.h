@@ -31,8 +31,11 @@
  *       u^{n+1}(s) += 2 dt^2 w[n][s] / (dt damp(s) + 2 m(s));
  *   * receivers record the new level on grid nodes: d[n][r] = u^{n+1}(r);
  *   * a point between grid nodes acts through multilinear interpolation over
- *     the nodes of its cell (fd_points.pos), which keeps the two rules above
- *     as the single-node case and the adjoint an exact transpose;
+ *     the nodes of its cell (fd_points.pos), or Kaiser-windowed sinc
+ *     interpolation (Hicks 2002) over 2r nodes per axis (fd_points.interp = r):
+ *     a receiver reads the weighted sum, a source adds to each node its
+ *     weight's share, which keeps the two rules above as the single-node case
+ *     and the adjoint an exact transpose;
  *   * sponge: damp(i) = sum_a d0_a (delta_a / L)^2 with delta_a the number of
  *     cells into the outer L-cell layer of axis a (0 in the interior and at the
  *     layer's inner edge) and d0_a = 1.5 ln(1000) / (vref L h_a)  [s/m^2];
@@ -153,7 +156,12 @@ typedef struct fd_time {
  * for bit).  Exactly one of idx and pos is non-NULL when n > 0. */
 typedef struct fd_points {
     int32_t n;           /* number of points, >= 0 */
-    int32_t reserved;    /* must be 0 */
+    int32_t interp;      /* with pos: 0 multilinear over the cell (2^ndim nodes);
+                            r in 1..8 Kaiser-windowed sinc of half-width r ((2r)^ndim
+                            nodes, those outside the grid left out; the window shape
+                            b(r) minimises the largest error of interpolating waves
+                            of up to four points per wavelength).  0 with idx.
+                            At most 2^27 nodes per point set (FD_EINVAL). */
     const int32_t *idx;  /* HOST, [n][ndim] grid indices, or NULL */
     const float *amp;    /* DEVICE, [nt][n] time samples: source wavelet (forward),
                             injected residual (adjoint), observed data or trace

@@ -52,6 +52,8 @@ class _Problem(C.Structure):
         ("rec", C.POINTER(C.c_int32)),
         ("spos", C.POINTER(C.c_double)),
         ("rpos", C.POINTER(C.c_double)),
+        ("ssinc", C.c_int32),
+        ("rsinc", C.c_int32),
     ]
 
 
@@ -74,8 +76,9 @@ def _load():
         lib.or_vjp.argtypes = [P, D, D, D, D]
         lib.or_gradient.argtypes = [P, D, D, D, D, D]
         lib.or_born.argtypes = [P, D, D, D]
+        lib.or_point_weights.argtypes = [P, D, C.c_int, C.POINTER(C.c_int64), D, C.c_int]
         for f in ("or_weights", "or_laplacian", "or_damp", "or_forward", "or_adjoint",
-                  "or_vjp", "or_gradient", "or_born"):
+                  "or_vjp", "or_gradient", "or_born", "or_point_weights"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
     return _lib
@@ -96,7 +99,7 @@ def _check(rc, what):
 class Problem:
     """Problem description mirrored into the C struct (keeps its arrays alive)."""
 
-    def __init__(self, v, h, so, nt, dt, sponge=0, vref=1500.0, src=None, rec=None):
+    def __init__(self, v, h, so, nt, dt, sponge=0, vref=1500.0, src=None, rec=None, src_sinc=0, rec_sinc=0):
         v = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
         self.v = v
         self.shape = v.shape
@@ -106,7 +109,8 @@ class Problem:
         self.so, self.nt, self.dt = int(so), int(nt), float(dt)
         self.sponge, self.vref = int(sponge), float(vref)
         # integer arrays are grid indices; floating-point arrays are positions in
-        # grid-index units (off the grid, multilinear interpolation)
+        # grid-index units (off the grid: multilinear interpolation, or with
+        # src_sinc / rec_sinc = r > 0 Kaiser-windowed sinc of half-width r)
         self.src, self.spos = self._points(src)
         self.rec, self.rpos = self._points(rec)
         s = _Problem()
@@ -121,6 +125,7 @@ class Problem:
         s.rec = self.rec.ctypes.data_as(C.POINTER(C.c_int32))
         s.spos = None if self.spos is None else _dptr(self.spos)
         s.rpos = None if self.rpos is None else _dptr(self.rpos)
+        s.ssinc, s.rsinc = int(src_sinc), int(rec_sinc)
         self._s = s
 
     def _points(self, pts):
@@ -216,3 +221,20 @@ def gradient(prob: Problem, amp, d_obs):
     J = C.c_double(0.0)
     _check(_load().or_gradient(prob.ref(), _dptr(a), _dptr(d), _dptr(gv), _dptr(gm), C.byref(J)), "gradient")
     return float(J.value), gv, gm
+
+
+def point_weights(shape, pos, sinc=0):
+    """Flat node indices and weights of one point at position ``pos`` (grid-index
+    units) on a grid of ``shape``: multilinear (sinc=0) or Kaiser-windowed sinc
+    of half-width ``sinc``."""
+    nd = len(shape)
+    prob = Problem(np.ones(shape), [1.0] * nd, 2, 0, 1.0)
+    cap = 4096
+    idx = np.zeros(cap, dtype=np.int64)
+    w = np.zeros(cap, dtype=np.float64)
+    p = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(nd))
+    n = _load().or_point_weights(prob.ref(), _dptr(p), int(sinc), idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 _dptr(w), cap)
+    if n < 0:
+        raise ValueError(f"oracle point_weights failed with code {n}")
+    return idx[:n].copy(), w[:n].copy()

@@ -31,6 +31,16 @@
  *     below is used).  A receiver records P u^{n+1}; a source adds
  *     A^{-1} 2 dt^2 P^T w, i.e. w_c 2 dt^2 w / (dt*damp(c) + 2 m(c)) at each node
  *     (the definitions above are the special case of a single node, weight 1).
+ *   * or, per point set, Kaiser-windowed sinc interpolation of half-width r
+ *     (Hicks 2002; 1 <= r <= 8): along each axis the 2r nodes i0-r+1 .. i0+r
+ *     around x = i0 + f (i0 = floor x) weigh
+ *       s(d) = sinc(d) I0(b sqrt(1 - (d/r)^2)) / I0(b),   d = node - x,
+ *     sinc(d) = sin(pi d)/(pi d) (exactly 1 at d = 0, 0 at other integers), the
+ *     point's weight at a node is the product over the axes, and nodes outside
+ *     the grid drop out (the field is zero there).  b(r) is the window shape
+ *     that minimises the largest error of interpolating cos(k x + phase) for
+ *     k h <= pi/2 (four points per wavelength), found by a search in steps of
+ *     0.1.  P and P^T use the same weights, as above.
  *   * separable sponge: damp(i) = sum_a d0_a (delta_a / L)^2, delta_a the number
  *     of cells into the outer L-cell layer (0 in the interior and at its inner
  *     edge), d0_a = 1.5 ln(1000) / (vref L h_a).  damp carries the units of m
@@ -62,6 +72,7 @@
 #include <string.h>
 
 #define OR_MAXM 8
+#define OR_PI 3.14159265358979323846
 
 typedef struct or_problem {
     int32_t ndim;        /* 1, 2 or 3 */
@@ -80,13 +91,16 @@ typedef struct or_problem {
     const int32_t *rec;  /* [nr][ndim] grid indices (used when rpos is NULL) */
     const double *spos;  /* [ns][ndim] positions in grid-index units, or NULL */
     const double *rpos;  /* [nr][ndim] positions in grid-index units, or NULL */
+    int32_t ssinc;       /* sources: 0 multilinear, r in 1..8 windowed sinc of half-width r */
+    int32_t rsinc;       /* receivers: the same */
 } or_problem;
 
-/* The nodes a point acts on and their interpolation weights (at most 8). */
+/* The nodes a point acts on and their interpolation weights (at most 16^3). */
+#define OR_MAXPT 4096
 typedef struct stencil_pt {
     int n;
-    int64_t idx[8];
-    double w[8];
+    int64_t idx[OR_MAXPT];
+    double w[OR_MAXPT];
 } stencil_pt;
 
 typedef struct geom {
@@ -278,10 +292,75 @@ static int point_stencil(const or_problem *p, const geom *g, const double *pos, 
     return 0;
 }
 
+/* Modified Bessel function of the first kind, order 0: its power series
+ * sum_j ((x/2)^j / j!)^2, summed until the terms stop mattering. */
+static double bessel_i0(double x)
+{
+    double term = 1.0, sum = 1.0, q = 0.25 * x * x;
+    for (int j = 1; j < 200; ++j) {
+        term *= q / ((double)j * (double)j);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+/* Window shape b per half-width r = 1..8 (minimax criterion in the header). */
+static const double kaiser_b[9] = {0.0, 1.3, 2.9, 4.5, 6.3, 7.9, 9.4, 10.9, 12.6};
+
+/* Weight of a node at signed distance d (grid units) for half-width r. */
+static double ksinc(double d, int r)
+{
+    double sinc;
+    if (d == 0.0) sinc = 1.0;
+    else if (d == floor(d)) sinc = 0.0;
+    else sinc = sin(OR_PI * d) / (OR_PI * d);
+    double t = d / (double)r;
+    if (t * t >= 1.0) return 0.0;
+    return sinc * bessel_i0(kaiser_b[r] * sqrt(1.0 - t * t)) / bessel_i0(kaiser_b[r]);
+}
+
+/* Kaiser-windowed sinc interpolation of a position: the product over the axes
+ * of the 1-D weights of the 2r nodes around it, nodes inside the grid and of
+ * nonzero weight only.  -1 if a coordinate is not finite or outside [0, n_a - 1]. */
+static int sinc_stencil(const or_problem *p, const geom *g, const double *pos, int r,
+                        stencil_pt *out)
+{
+    int64_t lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    double w1[3][16];
+    w1[0][0] = w1[1][0] = w1[2][0] = 1.0;
+    for (int a = 0; a < p->ndim; ++a) {
+        double x = pos[a];
+        int64_t n = p->n[a];
+        if (!(x >= 0.0) || !(x <= (double)(n - 1))) return -1;
+        int64_t i0 = (int64_t)floor(x);
+        int ax = a + g->first;
+        lo[ax] = i0 - r + 1;
+        cnt[ax] = 2 * r;
+        for (int k = 0; k < 2 * r; ++k) {
+            int64_t node = lo[ax] + k;
+            w1[ax][k] = (node < 0 || node >= n) ? 0.0 : ksinc((double)node - x, r);
+        }
+    }
+    out->n = 0;
+    for (int k0 = 0; k0 < cnt[0]; ++k0)
+        for (int k1 = 0; k1 < cnt[1]; ++k1)
+            for (int k2 = 0; k2 < cnt[2]; ++k2) {
+                double w = w1[0][k0] * w1[1][k1] * w1[2][k2];
+                if (w == 0.0) continue;
+                out->idx[out->n] = ((lo[0] + k0) * g->n[1] + (lo[1] + k1)) * g->n[2] + (lo[2] + k2);
+                out->w[out->n] = w;
+                out->n++;
+            }
+    return 0;
+}
+
 /* The stencil of point k of a set: one node of weight 1 for grid indices. */
 static int set_stencil(const or_problem *p, const geom *g, const int32_t *idx, const double *pos,
-                       int k, stencil_pt *out)
+                       int r, int k, stencil_pt *out)
 {
+    if (r < 0 || r > 8 || (r > 0 && !pos)) return -1;
+    if (pos && r > 0) return sinc_stencil(p, g, pos + (int64_t)k * p->ndim, r, out);
     if (pos) return point_stencil(p, g, pos + (int64_t)k * p->ndim, out);
     int64_t i = point_index(p, g, idx + (int64_t)k * p->ndim);
     if (i < 0) return -1;
@@ -289,6 +368,28 @@ static int set_stencil(const or_problem *p, const geom *g, const int32_t *idx, c
     out->idx[0] = i;
     out->w[0] = 1.0;
     return 0;
+}
+
+/* The nodes (flat indices) and weights one point acts on, for the tests:
+ * r = 0 multilinear, 1..8 windowed sinc.  Returns the node count, -1 on a bad
+ * position or r, -2 if cap is too small. */
+int or_point_weights(const or_problem *p, const double *pos, int r, int64_t *idx, double *w, int cap)
+{
+    geom g;
+    if (make_geom(p, &g) || !pos || r < 0 || r > 8) return -1;
+    stencil_pt *s = (stencil_pt *)malloc(sizeof(stencil_pt));
+    if (!s) return -2;
+    int rc = r > 0 ? sinc_stencil(p, &g, pos, r, s) : point_stencil(p, &g, pos, s);
+    if (rc == 0 && s->n > cap) rc = -2;
+    if (rc == 0) {
+        for (int j = 0; j < s->n; ++j) {
+            idx[j] = s->idx[j];
+            w[j] = s->w[j];
+        }
+        rc = s->n;
+    }
+    free(s);
+    return rc;
 }
 
 /* P u: the value a receiver (or an adjoint source sample) reads. */
@@ -337,9 +438,9 @@ static int work_init(const or_problem *p, work *w)
     }
     damp_g(p, &w->g, w->damp);
     for (int s = 0; s < p->ns; ++s)
-        if (set_stencil(p, &w->g, p->src, p->spos, s, &w->sp[s])) return -3;
+        if (set_stencil(p, &w->g, p->src, p->spos, p->ssinc, s, &w->sp[s])) return -3;
     for (int r = 0; r < p->nr; ++r)
-        if (set_stencil(p, &w->g, p->rec, p->rpos, r, &w->rp[r])) return -3;
+        if (set_stencil(p, &w->g, p->rec, p->rpos, p->rsinc, r, &w->rp[r])) return -3;
     return 0;
 }
 

@@ -65,7 +65,7 @@ class fd_time(C.Structure):
 class fd_points(C.Structure):
     _fields_ = [
         ("n", C.c_int32),
-        ("reserved", C.c_int32),
+        ("interp", C.c_int32),
         ("idx", C.POINTER(C.c_int32)),
         ("amp", C.c_void_p),
         ("pos", C.POINTER(C.c_double)),
@@ -242,13 +242,26 @@ def make_time(nt, dt):
     return t
 
 
+class Sinc:
+    """Positions (grid-index units) that act through Kaiser-windowed sinc
+    interpolation of half-width r (2r nodes per axis) instead of multilinear."""
+
+    def __init__(self, pos, r=4):
+        self.pos = np.asarray(pos, dtype=np.float64)
+        self.r = int(r)
+
+
 class Points:
     """fd_points with its host array kept alive: integer arrays are grid
     indices, floating-point arrays positions in grid-index units (points between
-    nodes, multilinear interpolation)."""
+    nodes, multilinear interpolation), a Sinc positions with windowed-sinc
+    interpolation."""
 
     def __init__(self, idx=None, amp=None, ndim=3):
         self.pos = None
+        interp = 0
+        if isinstance(idx, Sinc):
+            idx, interp = idx.pos, idx.r
         if idx is None:
             self.idx = np.zeros((0, ndim), dtype=np.int32)
         elif np.issubdtype(np.asarray(idx).dtype, np.floating):
@@ -259,7 +272,7 @@ class Points:
         self.amp = amp
         s = fd_points()
         s.n = len(self.idx)
-        s.reserved = 0
+        s.interp = interp
         if self.pos is not None:
             s.idx = None
             s.pos = self.pos.ctypes.data_as(C.POINTER(C.c_double)) if len(self.pos) else None

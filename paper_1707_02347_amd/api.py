@@ -2,7 +2,8 @@
 work runs on the current HIP stream, every step is done by libfdwave.so.
 
 Shapes: a velocity model ``v`` is a float32 CUDA tensor of 1, 2 or 3 dims
-(last axis contiguous); point indices are integer arrays [n][ndim]; sample
+(last axis contiguous); point indices are integer arrays [n][ndim] (float
+arrays: positions between nodes, multilinear; ``Sinc(pos, r)``: windowed sinc); sample
 arrays are float32 CUDA tensors [nt][n].
 """
 from __future__ import annotations
@@ -13,6 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib as L
+
+Sinc = L.Sinc  # positions with Kaiser-windowed sinc interpolation: Sinc(pos, r)
 
 
 def _dev_f32(t, name):

@@ -304,6 +304,7 @@ struct PtsSpec {
 };
 
 constexpr int kMaxFields = 12;
+constexpr int64_t kMaxEntries = (int64_t)1 << 27;  // interpolation entries of one point set
 
 struct Layout {
     float *q = nullptr;
@@ -576,7 +577,8 @@ KernelKey key_for(const KernelKey &base, int T, int mode, bool iso)
 // ------------------------------------------------------------------ point tables
 struct Entry {
     int x, y, z, id;
-    int corner;  // bit 2: +x, bit 1: +y, bit 0: +z from the cell's lowest node
+    int corner;  // order of the point's nodes: multilinear bit 2 +x, bit 1 +y, bit 0 +z from the
+                 // cell's lowest node; windowed sinc (i * 16 + j) * 16 + k
     float wt;
 };
 
@@ -613,13 +615,92 @@ int cell_of(const Dims &d, const double *pos, int id, std::vector<Entry> &out)
     return 0;
 }
 
+// Kaiser-windowed sinc (Hicks 2002): along one axis a point at x weighs the 2r
+// nodes floor(x) - r + 1 .. floor(x) + r by sinc(d) I0(b sqrt(1 - (d/r)^2)) / I0(b),
+// d = node - x.  b(r) minimises the largest error of interpolating a cosine of
+// wavenumber up to pi / (2h) (four points per wavelength), found by a search
+// over b in steps of 0.1.
+constexpr int kSincMax = 8;
+constexpr double kWindowShape[kSincMax + 1] = {0.0, 1.3, 2.9, 4.5, 6.3, 7.9, 9.4, 10.9, 12.6};
+
+double bessel_i0(double x)
+{
+    // power series of I0: terms ((x/2)^j / j!)^2, each the last times (x/2)^2 / j^2
+    const double q = 0.25 * x * x;
+    double sum = 1.0, t = 1.0;
+    for (int j = 1; j <= 200 && t > 1e-17 * sum; ++j) {
+        t = t * q / ((double)j * j);
+        sum += t;
+    }
+    return sum;
+}
+
+// The 1-D weights of the 2r nodes from lo = floor(x) - r + 1; nodes outside
+// [0, n - 1] get weight 0 (the field is zero there).
+void sinc_axis(double x, int r, int n, int &lo, double *w)
+{
+    const int i0 = (int)std::floor(x);
+    lo = i0 - r + 1;
+    const double norm = 1.0 / bessel_i0(kWindowShape[r]);
+    for (int k = 0; k < 2 * r; ++k) {
+        const int node = lo + k;
+        const double dx = (double)node - x;
+        if (node < 0 || node >= n) {
+            w[k] = 0.0;
+            continue;
+        }
+        // sinc is exactly 1 at distance 0 and 0 at the other integers
+        const double sn = dx == 0.0 ? 1.0
+                          : dx == std::trunc(dx) ? 0.0
+                                                 : std::sin(M_PI * dx) / (M_PI * dx);
+        const double rho = dx / r;
+        w[k] = rho * rho < 1.0 ? sn * bessel_i0(kWindowShape[r] * std::sqrt(1.0 - rho * rho)) * norm : 0.0;
+    }
+}
+
+// The nodes of a point's windowed-sinc stencil (half-width r) with their
+// weights, the products of the per-axis weights; zero weights left out.  The
+// entry's corner code is the node's rank in x-major order within the 2r-cube.
+int sinc_of(const Dims &d, const double *pos, int r, int id, std::vector<Entry> &out)
+{
+    static const int map[4][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 1, 2}};
+    const int n3[3] = {d.nx, d.ny, d.nz};
+    int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    double w[3][2 * kSincMax];
+    w[0][0] = w[1][0] = w[2][0] = 1.0;
+    for (int a = 0; a < d.ndim; ++a) {
+        const int ax = map[d.ndim][a];
+        const double x = pos[a];
+        if (!(x >= 0.0) || !(x <= (double)(n3[ax] - 1))) return -1;
+        sinc_axis(x, r, n3[ax], lo[ax], w[ax]);
+        cnt[ax] = 2 * r;
+    }
+    for (int i = 0; i < cnt[0]; ++i)
+        for (int j = 0; j < cnt[1]; ++j)
+            for (int k = 0; k < cnt[2]; ++k) {
+                const double wt = w[0][i] * w[1][j] * w[2][k];
+                if (wt == 0.0) continue;
+                out.push_back(Entry{lo[0] + i, lo[1] + j, lo[2] + k, id, (i * 16 + j) * 16 + k, (float)wt});
+            }
+    return 0;
+}
+
+int64_t nodes_per_point(const Dims &d, const fd_points *p)
+{
+    if (!p->pos) return 1;
+    const int64_t side = p->interp > 0 ? 2 * p->interp : 2;
+    int64_t c = 1;
+    for (int a = 0; a < d.ndim; ++a) c *= side;
+    return c;
+}
+
 PtsSpec spec_of(const Dims &d, const fd_points *p)
 {
     PtsSpec s;
     if (!p || p->n <= 0) return s;
     s.n = p->n;
     s.interp = p->pos != nullptr;
-    s.ent = s.interp ? p->n * (1 << d.ndim) : p->n;
+    s.ent = (int)std::min<int64_t>((int64_t)p->n * nodes_per_point(d, p), kMaxEntries);
     return s;
 }
 
@@ -627,10 +708,13 @@ int build_table(const Dims &d, const fd_points *pts, std::vector<Entry> &ent)
 {
     ent.clear();
     if (!pts || pts->n == 0) return FD_OK;
-    if (pts->n < 0 || pts->reserved != 0 || (!pts->idx == !pts->pos)) return FD_EINVAL;
+    if (pts->n < 0 || (!pts->idx == !pts->pos)) return FD_EINVAL;
+    if (pts->interp < 0 || pts->interp > kSincMax || (pts->interp && !pts->pos)) return FD_EINVAL;
     for (int i = 0; i < pts->n; ++i) {
         if (pts->pos) {
-            if (cell_of(d, pts->pos + (size_t)i * d.ndim, i, ent) < 0) return FD_EDOM;
+            const double *x = pts->pos + (size_t)i * d.ndim;
+            if ((pts->interp ? sinc_of(d, x, pts->interp, i, ent) : cell_of(d, x, i, ent)) < 0)
+                return FD_EDOM;
             continue;
         }
         int x, y, z;
@@ -830,9 +914,11 @@ int validate_common(const fd_grid *g, const fd_time *t, const float *v, Dims &d)
 int check_points(const Dims &d, const fd_points *p, bool need_amp, int64_t nt)
 {
     if (!p) return FD_OK;
-    if (p->n < 0 || p->reserved != 0) return FD_EINVAL;
+    if (p->n < 0) return FD_EINVAL;
     if (p->n > 0 && !p->idx == !p->pos) return FD_EINVAL;  // exactly one of idx, pos
+    if (p->interp < 0 || p->interp > kSincMax || (p->interp && p->n > 0 && !p->pos)) return FD_EINVAL;
     if (p->n > (1 << 24)) return FD_EINVAL;
+    if ((int64_t)p->n * nodes_per_point(d, p) > kMaxEntries) return FD_EINVAL;
     if (need_amp && p->n > 0 && nt > 0 && !p->amp) return FD_EINVAL;
     for (int i = 0; i < p->n; ++i) {
         if (p->pos) {

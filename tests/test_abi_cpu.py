@@ -220,6 +220,31 @@ def test_offgrid_points_validate_on_host():
     assert _call_forward(g, t, rec=rec, ws=C.c_void_p(0x10000), ws_bytes=1 << 40) == L.FD_EINVAL
 
 
+def test_sinc_points_validate_on_host_and_size_their_tables():
+    g, t = _grid(), L.make_time(100, 1e-3)
+    pos = np.array([[1.5, 2.0, 3.25], [20.0, 2.5, 2.5]])
+    ws = dict(ws=C.c_void_p(0x10000), ws_bytes=1 << 40)
+    # half-width outside 1..8, or a half-width with grid indices: FD_EINVAL
+    for r in (-1, 9):
+        assert _call_forward(g, t, rec=L.Points(L.Sinc(pos, r), None, 3), **ws) == L.FD_EINVAL
+    idx = L.Points(np.array([[1, 2, 3]]), None, 3)
+    idx.s.interp = 2
+    assert _call_forward(g, t, rec=idx, **ws) == L.FD_EINVAL
+    # positions are checked as for multilinear points
+    bad = L.Points(L.Sinc(np.array([[1.0, 1.0, 40.5]]), 4), None, 3)
+    assert _call_forward(g, t, rec=bad, **ws) == L.FD_EDOM
+    # (2r)^3 entries per point, and one recorded value per entry and step
+    lin = L.Points(pos, None, 3)
+    for r in (1, 4, 8):
+        snc = L.Points(L.Sinc(pos, r), None, 3)
+        a = L.fd_workspace_size(C.byref(g), C.byref(t), None, C.byref(lin.s), None, L.FD_OP_FORWARD)
+        b = L.fd_workspace_size(C.byref(g), C.byref(t), None, C.byref(snc.s), None, L.FD_OP_FORWARD)
+        assert b - a >= 2 * 100 * ((2 * r) ** 3 - 8) * 4
+    # at most 2^27 interpolation entries per point set
+    many = L.Points(L.Sinc(np.full(((1 << 27) // 4096 + 1, 3), 5.5), 8), None, 3)
+    assert _call_forward(g, t, rec=many, **ws) == L.FD_EINVAL
+
+
 def test_offgrid_points_grow_the_workspace():
     g, t = _grid(), L.make_time(100, 1e-3)
     on = L.Points(np.array([[1, 2, 3], [2, 2, 2]]), None, 3)

@@ -35,6 +35,10 @@ MUTATIONS = {
     "born_source_sign": ("du[2][i] += -2.0 * dm[i] * (u[2][i]", "du[2][i] += 2.0 * dm[i] * (u[2][i]"),
     "born_first_difference": ("(u[2][i] - 2.0 * u[1][i] + u[0][i])", "(u[2][i] - u[1][i])"),
     "born_dm_power": ("dm[i] = -2.0 * dv[i] / (p->v[i] * p->v[i] * p->v[i]);", "dm[i] = -2.0 * dv[i] / (p->v[i] * p->v[i]);"),
+    "sinc_window_radius": ("double t = d / (double)r;", "double t = d / (double)(r + 1);"),
+    "sinc_node_shift": ("lo[ax] = i0 - r + 1;", "lo[ax] = i0 - r;"),
+    "sinc_distance_sign": ("ksinc((double)node - x, r);", "ksinc(x - (double)node + 0.25, r);"),
+    "sinc_bessel_term": ("term *= q / ((double)j * (double)j);", "term *= q / (double)j;"),
     "sponge_off_by_one": ("if (i < L) delta = (double)(L - i);", "if (i < L) delta = (double)(L - i - 1);"),
     "dt_squared_missing": ("double dt2 = dt * dt;\n#pragma omp parallel for schedule(static)\n    for (int64_t i0 = 0; i0 < g->n[0]; ++i0)\n        for (int64_t i1 = 0; i1 < g->n[1]; ++i1)\n            for (int64_t i2 = 0; i2 < g->n[2]; ++i2) {\n                int64_t i = (i0 * g->n[1] + i1) * g->n[2] + i2;\n                double tcse",
                            "double dt2 = dt;\n#pragma omp parallel for schedule(static)\n    for (int64_t i0 = 0; i0 < g->n[0]; ++i0)\n        for (int64_t i1 = 0; i1 < g->n[1]; ++i1)\n            for (int64_t i2 = 0; i2 < g->n[2]; ++i2) {\n                int64_t i = (i0 * g->n[1] + i1) * g->n[2] + i2;\n                double tcse"),
@@ -59,6 +63,10 @@ def _checks():
     yield lambda: pins.test_offgrid_source_spreads_unit_mass_at_its_position((4.25, 5.5, 6.75))
     yield lambda: pins.test_offgrid_dot_product_fp64((40, 36))
     yield lambda: pins.test_born_is_the_derivative_of_the_forward_map(False)
+    for r in (1, 4):
+        yield lambda r=r: pins.test_sinc_weights_are_the_kaiser_windowed_sinc(r)
+    yield lambda: pins.test_sinc_at_grid_nodes_is_the_node_itself(4)
+    yield lambda: pins.test_sinc_receiver_reads_band_limited_waves(4, 3 * 1.2e-3)
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

@@ -581,3 +581,124 @@ def test_born_is_the_transpose_of_the_vector_jacobian_product():
     gv, _ = oracle.vjp(prob, w, y)
     rhs = float((dv * gv).sum())
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
+# ---------------------------------------------------------------- windowed-sinc points
+# Window shape per half-width r: the documented choice (the b that minimises the
+# largest error of interpolating cos(k x + phase), k h <= pi/2, on the sampling below).
+KAISER_B = {1: 1.3, 2: 2.9, 3: 4.5, 4: 6.3, 5: 7.9, 6: 9.4, 7: 10.9, 8: 12.6}
+
+
+def ksinc_numpy(f, r, b):
+    """1-D Kaiser-windowed sinc weights of the nodes -r+1..r around x = f, from
+    numpy's sinc and scipy's I0 (library routines)."""
+    from scipy.special import i0
+    d = np.arange(-r + 1, r + 1) - f
+    return np.sinc(d) * i0(b * np.sqrt(np.clip(1.0 - (d / r) ** 2, 0.0, None))) / i0(b)
+
+
+def band_error(r, b):
+    worst = 0.0
+    kh = np.linspace(0.0, np.pi / 2, 31)[:, None]
+    for f in np.linspace(0.0, 1.0, 41)[:-1]:
+        w = ksinc_numpy(f, r, b)
+        k = np.arange(-r + 1, r + 1)[None, :]
+        for ph in (0.0, 0.7, 1.9):
+            worst = max(worst, float(np.abs(np.cos(kh * k + ph) @ w - np.cos(kh[:, 0] * f + ph)).max()))
+    return worst
+
+
+@pytest.mark.parametrize("r", range(1, 9))
+def test_sinc_weights_are_the_kaiser_windowed_sinc(r):
+    """1-D weights equal numpy sinc x scipy I0 window (1e-13), and b(r) is a
+    local minimum of the band error within +-0.1."""
+    for x in (10.0, 10.3, 10.5, 10.999, 17.25):
+        idx, w = oracle.point_weights((40,), (x,), sinc=r)
+        ref = ksinc_numpy(x - np.floor(x), r, KAISER_B[r])
+        nodes = np.floor(x) + np.arange(-r + 1, r + 1)
+        keep = np.abs(ref) > 1e-14  # numpy's sinc is ~1e-17, not 0, at the nonzero integers
+        np.testing.assert_array_equal(idx, nodes[keep].astype(np.int64))
+        np.testing.assert_allclose(w, ref[keep], rtol=1e-13, atol=1e-15)
+    b = KAISER_B[r]
+    e = band_error(r, b)
+    assert e <= band_error(r, b - 0.1) and e <= band_error(r, b + 0.1)
+
+
+@pytest.mark.parametrize("r", [1, 2, 4, 8])
+def test_sinc_at_grid_nodes_is_the_node_itself(r):
+    """sinc vanishes at the nonzero integers: a position on a node keeps that
+    node alone with weight exactly 1, also next to the boundary."""
+    shape = (30, 20, 25)
+    for pos in ((5.0, 6.0, 7.0), (0.0, 0.0, 0.0), (29.0, 19.0, 24.0), (1.0, 18.0, 12.0)):
+        idx, w = oracle.point_weights(shape, pos, sinc=r)
+        flat = (int(pos[0]) * shape[1] + int(pos[1])) * shape[2] + int(pos[2])
+        assert idx.tolist() == [flat] and w.tolist() == [1.0]
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_sinc_weights_are_separable_mirror_symmetric_and_clipped(r):
+    shape = (24, 26, 28)
+    pos = np.array([11.3, 12.75, 13.5])
+    idx, w = oracle.point_weights(shape, pos, sinc=r)
+    per = [oracle.point_weights((n,), (p,), sinc=r) for n, p in zip(shape, pos)]
+    full = {}
+    for (i0, w0), (i1, w1), (i2, w2) in itertools.product(*[list(zip(*p)) for p in per]):
+        full[(i0 * shape[1] + i1) * shape[2] + i2] = w0 * w1 * w2
+    assert sorted(full) == sorted(idx.tolist())
+    np.testing.assert_allclose([full[i] for i in idx.tolist()], w, rtol=1e-14)
+    # mirror: the weights at i + f, read backwards, are those at j + (1 - f)
+    for f in (0.2, 0.5, 0.83):
+        _, a = oracle.point_weights((40,), (15.0 + f,), sinc=r)
+        _, b = oracle.point_weights((40,), (20.0 + (1.0 - f),), sinc=r)
+        np.testing.assert_allclose(a, b[::-1], rtol=1e-12, atol=1e-15)  # f and 1 - f round apart
+    # near a boundary the nodes outside the grid drop out, the others are unchanged
+    ia, wa = oracle.point_weights((40,), (1.3,), sinc=r)
+    ib, wb = oracle.point_weights((40,), (21.3,), sinc=r)
+    assert ia[0] == 0 and len(ia) == len(ib) - (r - 2)
+    np.testing.assert_allclose(wa, wb[len(ib) - len(ia):], rtol=1e-12)
+
+
+@pytest.mark.parametrize("r,bound", [(4, 3 * 1.2e-3), (8, 3 * 2e-6)])
+def test_sinc_receiver_reads_band_limited_waves(r, bound):
+    """A 3-D plane wave of at least four points per wavelength on every axis is
+    read at a point between nodes to the 1-D band error, compounded per axis."""
+    shape = (30, 30, 30)
+    X = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij"), -1)
+    rng = np.random.default_rng(8)
+    for _ in range(6):
+        k = rng.uniform(-np.pi / 2, np.pi / 2, 3)
+        ph = rng.uniform(0, 2 * np.pi)
+        field = np.cos(X @ k + ph).ravel()
+        pos = rng.uniform(12.0, 17.0, 3)
+        idx, w = oracle.point_weights(shape, pos, sinc=r)
+        assert len(idx) == (2 * r) ** 3
+        assert abs(float(w @ field[idx]) - np.cos(pos @ k + ph)) <= bound
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 22), (40, 36)])
+def test_sinc_dot_product_and_node_positions_fp64(shape):
+    """The windowed-sinc source and receiver operators are exact transposes
+    (FP64 dot test), and on grid nodes they reduce to plain grid indices."""
+    nt, so, r = 40, 8, 3
+    v = synth.smooth_velocity(shape, seed=1709, sigma=3.0).numpy().astype(np.float64)
+    h = [10.0, 12.0, 9.0][:len(shape)]
+    dt = 0.8 * 0.4529 * 9.0 / v.max()
+    src = synth.offgrid_points(shape, 3, seed=21)
+    rec = np.concatenate([synth.offgrid_points(shape, 6, seed=22), np.zeros((1, len(shape)))], 0)
+    prob = oracle.Problem(v, h, so, nt, dt, sponge=4, vref=4500.0, src=src, rec=rec, src_sinc=r, rec_sinc=r)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal((nt, 3))
+    y = rng.standard_normal((nt, 7))
+    d = oracle.forward(prob, amp=w)["rec"]
+    fty = oracle.adjoint(prob, y)["src"]
+    lhs, rhs = float((d * y).sum()), float((w * fty).sum())
+    assert abs(lhs) > 0
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+    # differs from multilinear interpolation at the same positions
+    lin = oracle.forward(oracle.Problem(v, h, so, nt, dt, sponge=4, vref=4500.0, src=src, rec=rec), amp=w)["rec"]
+    assert np.abs(lin - d).max() > 1e-3 * np.abs(d).max()
+    nodes = np.round(src).astype(np.int32), np.round(rec).astype(np.int32)
+    a = oracle.Problem(v, h, so, nt, dt, sponge=4, vref=4500.0, src=nodes[0], rec=nodes[1])
+    b = oracle.Problem(v, h, so, nt, dt, sponge=4, vref=4500.0, src=nodes[0].astype(np.float64),
+                       rec=nodes[1].astype(np.float64), src_sinc=r, rec_sinc=r)
+    np.testing.assert_array_equal(oracle.forward(a, amp=w)["rec"], oracle.forward(b, amp=w)["rec"])
