@@ -113,9 +113,13 @@ __global__ void k_gather(const float *etr, int64_t rows, int cnt, const int32_t 
     if (i >= rows * npts) return;
     const int64_t row = i / npts;
     const int p = (int)(i - row * npts);
-    float acc = 0.0f;
-    for (int k = pptr[p]; k < pptr[p + 1]; ++k) acc = fmaf(wt[pent[k]], etr[row * cnt + pent[k]], acc);
-    out[i] = acc * rscale;
+    // FP64 accumulation, one rounding at the end: a windowed-sinc point sums
+    // up to 4096 products of alternating sign, several times larger than the
+    // result, which an FP32 sum would round at every term
+    double acc = 0.0;
+    for (int k = pptr[p]; k < pptr[p + 1]; ++k)
+        acc = fma((double)wt[pent[k]], (double)etr[row * cnt + pent[k]], acc);
+    out[i] = (float)(acc * (double)rscale);
 }
 
 hipError_t launch_gather(const float *etr, int64_t rows, int cnt, const int32_t *pptr,
