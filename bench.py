@@ -300,13 +300,18 @@ def offgrid(cs):
 
 
 def offgrid_rates(cs):
-    """cfg2 sweep with 256 receivers, on grid nodes and between them (GPts/s)."""
+    """cfg2 sweep with 256 receivers, on grid nodes and between them (GPts/s):
+    multilinear (8 nodes per point) and Kaiser-windowed sinc of half-width 4
+    (512 nodes per point)."""
     import synth
+    from paper_1707_02347_amd import api
 
     on = dict(cs, rec=synth.receiver_line(cs["v"].shape, 256, depth=20))
+    off = offgrid(on)
+    sinc = dict(off, src=api.Sinc(off["src"], 4), rec=api.Sinc(off["rec"], 4))
     npts = int(np.prod(cs["v"].shape))
     out = {}
-    for name, c in (("on_grid_256rec", on), ("off_grid_256rec", offgrid(on))):
+    for name, c in (("on_grid_256rec", on), ("off_grid_256rec", off), ("sinc4_256rec", sinc)):
         med, _, _ = time_sweeps(c, launch_options("cfg2"), 3, 1)
         out[name] = round(npts * c["nt"] / ((med - setup_ms(c, launch_options("cfg2"))) * 1e-3) / 1e9, 2)
     return out

@@ -901,6 +901,28 @@ bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
     return fits(a.inj) && fits(a.rec);
 }
 
+// A point table no chunk could stage: more than kPtsCap entries within some
+// kHeavySpan consecutive planes (dense receiver planes, windowed-sinc points by
+// the hundred).  Walked inside the tiled kernel it would cost one serial
+// iteration per entry on every plane that holds them, so the steps take
+// another route: receivers are recorded by a per-entry kernel after each
+// single-level pass; an injected table sends the step through the untiled
+// kernel and its per-entry injection.  Both routes give the same bits.
+constexpr int kHeavySpan = 32;
+
+bool heavy_table(const Ctx &c, const PointTable &t)
+{
+    if (t.cnt <= kPtsCap) return false;
+    const std::vector<int32_t> *hx = (t.xptr == c.L.src.xptr)   ? &c.hxs
+                                     : (t.xptr == c.L.rec.xptr) ? &c.hxr
+                                                                : nullptr;
+    if (!hx || hx->size() < 2) return false;
+    const int nx = (int)hx->size() - 1;
+    for (int x = 0; x < nx; ++x)
+        if ((*hx)[std::min(x + kHeavySpan, nx)] - (*hx)[x] > kPtsCap) return true;
+    return false;
+}
+
 int validate_common(const fd_grid *g, const fd_time *t, const float *v, Dims &d)
 {
     int rc = make_dims(g, d);
@@ -1067,7 +1089,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.dslot0 = so.dslot_first + (int64_t)so.ddir * s;
         a.ddir = so.ddir;
         a.g = c.L.g;
-        if (c.plan.variant == FD_VARIANT_NAIVE) {
+        if (c.plan.variant == FD_VARIANT_NAIVE || heavy_table(c, a.inj)) {
             a.u0 = st.cur;
             a.um = st.prev;
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
@@ -1086,7 +1108,9 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             s += 1;
             continue;
         }
-        const int T = (nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+        // receivers recorded after the pass need its output level in memory
+        const bool rsep = heavy_table(c, a.rec);
+        const int T = (!rsep && nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
         const bool iso = c.base.w.iso != 0;
         KernelKey k = (T == c.plan.key.T && so.mode == kPlain) ? c.plan.key
                                                                 : key_for(c.plan.key, T, so.mode, iso);
@@ -1113,9 +1137,12 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.remap = c.plan.remap ? 1 : 0;
         a.alt = c.plan.alt ? 1 : 0;
         a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
+        const SweepArgs ar = a;
+        if (rsep) a.rec = PointTable{};
         a.ps = stage_points(c, k, a) ? 1 : 0;
         supertile(k, a);
         c.ex.pass(k, a, c.plan.loads);
+        if (rsep) c.ex.call([ar, o1](hipStream_t s) { return launch_record(ar, o1, ar.step0, s); });
         if (Tk == 1) swap_in(st, o1, st.cur);
         else swap_in(st, o1, o2);
         s += Tk;
@@ -1526,7 +1553,8 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
         // (32 B per point instead of 44), else two passes per step
         const KernelKey fk = key_for(c.plan.key, 1, kBornFused, c.base.w.iso != 0);
         const bool fused = c.plan.variant != FD_VARIANT_NAIVE && fk.mode == kBornFused &&
-                           stream_has(fk, c.base.w.iso != 0);
+                           stream_has(fk, c.base.w.iso != 0) && !heavy_table(c, bg.inj) &&
+                           !heavy_table(c, pb.rec);
         if (fused) {
             SweepArgs fa = c.base;
             fa.amp = src ? src->amp : nullptr;
