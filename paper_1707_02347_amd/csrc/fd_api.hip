@@ -882,7 +882,7 @@ struct Ctx {
 // the capacity, since the staged form of the kernel has no other walk.
 bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
 {
-    if (!points_stageable(k.PY, k.NW)) return false;
+    if (!points_stageable(k.M, k.T, k.PY, k.NW)) return false;
     if (a.inj.cnt <= kStageMin && a.rec.cnt <= kStageMin) return false;
     const int cap = kPtsCap / k.T, H = (k.T - 1) * k.M;
     auto fits = [&](const PointTable &t) {

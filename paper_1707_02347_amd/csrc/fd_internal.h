@@ -105,7 +105,7 @@ struct SweepArgs {
 // the walk in memory is kept (a lone source costs it nothing).
 constexpr int kPtsCap = 512;
 constexpr int kStageMin = 32;
-constexpr bool points_stageable(int PY, int NW) { return NW < 16 && PY <= 4; }
+constexpr bool points_stageable(int M, int T, int PY, int NW) { return NW < 16 && PY <= 4 && M * T < 16; }
 
 // kBorn: the perturbation wavefield of Born modelling, whose update carries
 // the volume source s * d2 inside the division: (num + s d2) / (1 + eta), with

@@ -183,7 +183,7 @@ struct StreamKernel {
         // out after the loop.
         // A node is coded (wave << 16) | (row in the wave << 8) | column.
         int i0, r0;
-        int icode[PC];
+        int iyz[PC];
         float isc[PC], iamp[T][PC];
         int rcode[PC], rdst[PC];
         float rval[T][PC];
@@ -330,10 +330,7 @@ struct StreamKernel {
             }
             if (istg)
                 for (int j = threadIdx.x; j < ie - ib; j += G::NT) {
-                    const int yz = a.inj.yz[ib + j];
-                    const int y = yz / a.nzp, rr = y - y1, cz = yz - y * a.nzp - z1;
-                    const bool own = rr >= 0 && rr < G::RY && cz >= 0 && cz < G::RZ;
-                    sm.icode[j] = own ? ((rr / PY) << 16) | ((rr % PY) << 8) | cz : -1;
+                    sm.iyz[j] = a.inj.yz[ib + j];
                     sm.isc[j] = a.inj.scale[ib + j];
                     const int id = a.inj.id[ib + j];
 #pragma unroll
@@ -712,30 +709,24 @@ struct StreamKernel {
                 if (jb < je) {
                     const float *arow = a.amp + (a.abase + (int64_t)a.adir * step) * a.inj.stride;
                     if constexpr (STAGE) {
+                        // staged: the plane's entries are sorted by (y, z), so
+                        // each thread finds the run of entries at its own node
+                        // by binary search and applies it in table order
                         const int s0 = __builtin_amdgcn_readfirstlane(sm.i0);
-                        const int sw = __builtin_amdgcn_readfirstlane(wv);
-                        // staged: up to 64 entries at a time sit in the lanes of
-                        // one LDS read; the walk reads them back with lane reads
-                        for (int j0 = jb; j0 < je; j0 += 64) {
-                            const int n = min(64, je - j0), k = j0 + lane - s0;
-                            int code = -1;
-                            float scl = 0.0f, wl = 0.0f;
-                            if (lane < n) {
-                                code = sm.icode[k];
-                                scl = sm.isc[k];
-                                wl = sm.iamp[t - 1][k];
-                            }
-                            for (int kk = 0; kk < n; ++kk) {
-                                const int ck = __builtin_amdgcn_readlane(code, kk);
-                                if (ck < 0 || (ck >> 16) != sw) continue;
-                                const int rk = (ck >> 8) & 0xff, lk = ck & 0xff, rr = sw * PY + rk;
-                                if (rr < lo || rr >= G::RY - lo || lk < lo || lk >= G::RZ - lo) continue;
-                                const float sc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scl), kk));
-                                const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), kk));
+                        const int kb = jb - s0, ke = je - s0;
 #pragma unroll
-                                for (int r = 0; r < PY; ++r)
-                                    if (r == rk && lane == lk) out[r] = fmaf(sc, w, out[r]);
+                        for (int r = 0; r < PY; ++r) {
+                            const int rr = wv * PY + r;
+                            const bool active = th.din[r] && zreg && rr >= lo && rr < G::RY - lo;
+                            const int key = (int)(th.bo[r] >> 2);
+                            int kl = kb, kh = ke;
+                            while (kl < kh) {
+                                const int km = (kl + kh) >> 1;
+                                if (sm.iyz[km] < key) kl = km + 1;
+                                else kh = km;
                             }
+                            for (int k = kl; active && k < ke && sm.iyz[k] == key; ++k)
+                                out[r] = fmaf(sm.isc[k], sm.iamp[t - 1][k], out[r]);
                         }
                     } else {
                         for (int j = jb; j < je; ++j) {
@@ -957,7 +948,7 @@ __global__ __launch_bounds__(64 * NW) void k_stream_grouped(const GroupEntry *__
 template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
 void issue_stream_p(const SweepArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    if constexpr (points_stageable(PY, NW)) {
+    if constexpr (points_stageable(M, T, PY, NW)) {
         if (a.ps) {
             hipLaunchKernelGGL((k_stream<M, T, PY, NW, MODE, ISO, NTL, true>), grid, block, 0, s, a);
             return;
@@ -992,7 +983,7 @@ template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL>
 void issue_grouped_p(bool ps, const GroupEntry *list, int nlist, int total, dim3 grid, dim3 block,
                      hipStream_t s)
 {
-    if constexpr (points_stageable(PY, NW)) {
+    if constexpr (points_stageable(M, T, PY, NW)) {
         if (ps) {
             hipLaunchKernelGGL((k_stream_grouped<M, T, PY, NW, MODE, ISO, NTL, true>), grid, block, 0,
                                s, list, nlist, total);
