@@ -47,7 +47,7 @@
     X(4, 1, 4, 8, 2, FDW_AG) X(4, 2, 4, 8, 0, FDW_A) X(4, 2, 2, 16, 0, FDW_AG)            \
     X(4, 3, 4, 8, 0, 0) X(4, 3, 2, 16, 0, 0)                      \
     X(4, 2, 4, 8, 1, FDW_G) X(4, 2, 4, 8, 2, FDW_G) X(4, 2, 2, 16, 1, FDW_G)              \
-    X(4, 2, 2, 16, 2, 0) X(4, 1, 4, 8, 3, FDW_A) X(4, 1, 4, 8, 4, FDW_A)
+    X(4, 2, 2, 16, 2, 0) X(4, 1, 4, 8, 3, FDW_A) X(4, 1, 4, 8, 4, FDW_A) X(4, 1, 2, 8, 4, FDW_A)
 
 #define FDW_CONFIGS_M8(X)                                                                  \
     X(8, 1, 8, 4, 0, FDW_AG) X(8, 1, 4, 4, 0, FDW_AG) X(8, 1, 8, 2, 0, 0)                  \
