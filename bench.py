@@ -429,9 +429,10 @@ def main():
                     help="only the headline tiled sweep (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
-    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8"], default=None,
+    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8", "born"], default=None,
                     help="only 20-step sweeps of one more workload, for profiling runs: cfg3 "
-                         "(512^3 so 16, tiled) or tblock-so8 (512^3 so 8, T = 1 then T = 2)")
+                         "(512^3 so 16, tiled), tblock-so8 (512^3 so 8, T = 1 then T = 2) or born "
+                         "(Born modelling on the headline grid, 256 receivers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -449,6 +450,18 @@ def main():
         ms = _timed(lambda: y.copy_(x), 5, 2)[0]
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return 0
+    if args.kernel_only == "born":
+        import synth
+
+        cs = workload("cfg2")
+        rec = synth.receiver_line(cs["v"].shape, 256, depth=20)
+        dv = 0.05 * (synth.blob_velocity(cs["v"], amp=1.0, width_frac=1.0 / 16.0) - cs["v"])
+        for _ in range(args.warmup + args.steps):
+            api.born(cs["v"], cs["h"], cs["so"], 20, cs["dt"], cs["src"], cs["amp"][:20].contiguous(), rec, dv,
+                     sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg2"))
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "born", "runs": args.warmup + args.steps, "steps": 20}), flush=True)
         return 0
     if args.kernel_only:
         import synth
