@@ -335,8 +335,9 @@ def born_rate(reps=2, warmup=1):
             "config": "256^3 so8, 500 steps, 256 receivers, dv = 5 % Gaussian blob of width N/16"}
 
 
-def gradient_rate(reps=2, warmup=1, off_grid=False, ckpt_every=50):
-    """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50)."""
+def gradient_rate(reps=2, warmup=1, off_grid=False, ckpt_every=50, sinc=0):
+    """cfg4: FWI gradients/s (256^3, so 8, 1000 steps, 256 receivers, checkpoint every 50);
+    off_grid: points between nodes (multilinear, or windowed sinc of half-width ``sinc``)."""
     import torch
 
     import synth
@@ -345,6 +346,8 @@ def gradient_rate(reps=2, warmup=1, off_grid=False, ckpt_every=50):
     cs = workload("cfg4")
     if off_grid:
         cs = offgrid(cs)
+        if sinc:
+            cs = dict(cs, src=api.Sinc(cs["src"], sinc), rec=api.Sinc(cs["rec"], sinc))
     vtrue = synth.blob_velocity(cs["v"], amp=0.05, width_frac=1.0 / 16.0)
     d_obs = api.forward(vtrue, cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], cs["amp"], cs["rec"],
                         sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg4"))["rec"]
@@ -565,6 +568,7 @@ def main():
         og = offgrid_rates(cs)
         g = gradient_rate(off_grid=True)
         og["cfg4_off_grid_gradients_per_s"] = g["gradients_per_s"]
+        og["cfg4_sinc4_gradients_per_s"] = gradient_rate(reps=1, off_grid=True, sinc=4)["gradients_per_s"]
         line["off_grid_points"] = og
         # the whole time axis stored (1000 second differences, 64 GB) instead of
         # checkpoints every 50 steps: no recomputation sweep
