@@ -905,9 +905,10 @@ bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
 // kHeavySpan consecutive planes (dense receiver planes, windowed-sinc points by
 // the hundred).  Walked inside the tiled kernel it would cost one serial
 // iteration per entry on every plane that holds them, so the steps take
-// another route: receivers are recorded by a per-entry kernel after each
-// single-level pass; an injected table sends the step through the untiled
-// kernel and its per-entry injection.  Both routes give the same bits.
+// another route (single-level passes): receivers are recorded by a per-entry
+// kernel after the pass; an injected table is added by one after a plain-mode
+// pass, which the untiled path's recording and second-difference or imaging
+// kernels follow.  Every route gives the same bits.
 constexpr int kHeavySpan = 32;
 
 bool heavy_table(const Ctx &c, const PointTable &t)
@@ -1089,7 +1090,14 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.dslot0 = so.dslot_first + (int64_t)so.ddir * s;
         a.ddir = so.ddir;
         a.g = c.L.g;
-        if (c.plan.variant == FD_VARIANT_NAIVE || heavy_table(c, a.inj)) {
+        // an injected table no chunk can stage: the tiled pass runs without it
+        // in the plain mode and the untiled path's injection, recording and
+        // second-difference or imaging kernels follow (its own order); only
+        // modes whose update itself needs the injected values fall back to the
+        // untiled step
+        const bool iheavy = heavy_table(c, a.inj);
+        const bool isep = iheavy && (so.mode == kPlain || so.mode == kSaveD2 || so.mode == kImaging);
+        if (c.plan.variant == FD_VARIANT_NAIVE || (iheavy && !isep)) {
             a.u0 = st.cur;
             a.um = st.prev;
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
@@ -1109,18 +1117,21 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             continue;
         }
         // receivers recorded after the pass need its output level in memory
-        const bool rsep = heavy_table(c, a.rec);
+        const bool rsep = isep || heavy_table(c, a.rec);
         const int T = (!rsep && nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
         const bool iso = c.base.w.iso != 0;
-        KernelKey k = (T == c.plan.key.T && so.mode == kPlain) ? c.plan.key
-                                                                : key_for(c.plan.key, T, so.mode, iso);
-        if (k.T != T) k = key_for(c.plan.key, 1, so.mode, iso);
+        const int kmode = isep ? (int)kPlain : so.mode;
+        KernelKey k = (T == c.plan.key.T && kmode == kPlain) ? c.plan.key
+                                                              : key_for(c.plan.key, T, kmode, iso);
+        if (k.T != T) k = key_for(c.plan.key, 1, kmode, iso);
         const int Tk = k.T;
         a.u0 = st.cur;
         a.um = st.prev;
         float *o1, *o2 = nullptr;
         if (Tk == 1) {
-            o1 = st.prev;  // in place: each point's u^{n-1} is read only by its owner
+            // in place: each point's u^{n-1} is read only by its owner (but a
+            // second difference saved after the pass needs u^{n-1} intact)
+            o1 = (isep && so.mode == kSaveD2) ? st.spare[0] : st.prev;
         } else {
             o1 = st.spare[0];
             o2 = st.spare[1];
@@ -1139,10 +1150,22 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
         const SweepArgs ar = a;
         if (rsep) a.rec = PointTable{};
+        if (isep) a.inj = PointTable{};
         a.ps = stage_points(c, k, a) ? 1 : 0;
         supertile(k, a);
         c.ex.pass(k, a, c.plan.loads);
-        if (rsep) c.ex.call([ar, o1](hipStream_t s) { return launch_record(ar, o1, ar.step0, s); });
+        if (rsep) {
+            const int mode = so.mode;
+            const float *cur = st.cur, *prev = st.prev;
+            float *d2 = a.d2 + a.dslot0 * d.Np;
+            c.ex.call([ar, o1, cur, prev, d2, mode, isep](hipStream_t s) {
+                hipError_t e = isep ? launch_inject(ar, o1, ar.step0, s) : hipSuccess;
+                if (e == hipSuccess) e = launch_record(ar, o1, ar.step0, s);
+                if (e == hipSuccess && isep && mode == kSaveD2) e = launch_save_d2(ar, o1, cur, prev, d2, s);
+                if (e == hipSuccess && isep && mode == kImaging) e = launch_imaging(ar, o1, d2, ar.g, s);
+                return e;
+            });
+        }
         if (Tk == 1) swap_in(st, o1, st.cur);
         else swap_in(st, o1, o2);
         s += Tk;
