@@ -880,25 +880,27 @@ struct Ctx {
 // can stage, a table large enough to be worth it, and every chunk's entries
 // (its planes, with the 2 (T - 1) M overlap planes of a time block) within
 // the capacity, since the staged form of the kernel has no other walk.
+bool fits_chunks(const Ctx &c, const KernelKey &k, const SweepArgs &a, const PointTable &t)
+{
+    if (t.cnt == 0) return true;
+    const int cap = kPtsCap / k.T, H = (k.T - 1) * k.M;
+    const std::vector<int32_t> *hx = (t.xptr == c.L.src.xptr)   ? &c.hxs
+                                     : (t.xptr == c.L.rec.xptr) ? &c.hxr
+                                                                : nullptr;
+    if (!hx || hx->size() != (size_t)a.nx + 1) return false;
+    for (int x0 = 0; x0 < a.nx; x0 += a.lx) {
+        const int xend = std::min(x0 + a.lx, a.nx);
+        const int c0 = std::max(x0 - H, 0), c1 = std::min(xend + H, a.nx);
+        if ((*hx)[c1] - (*hx)[c0] > cap) return false;
+    }
+    return true;
+}
+
 bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
 {
     if (!points_stageable(k.M, k.T, k.PY, k.NW)) return false;
     if (a.inj.cnt <= kStageMin && a.rec.cnt <= kStageMin) return false;
-    const int cap = kPtsCap / k.T, H = (k.T - 1) * k.M;
-    auto fits = [&](const PointTable &t) {
-        if (t.cnt == 0) return true;
-        const std::vector<int32_t> *hx = (t.xptr == c.L.src.xptr)   ? &c.hxs
-                                         : (t.xptr == c.L.rec.xptr) ? &c.hxr
-                                                                    : nullptr;
-        if (!hx || hx->size() != (size_t)a.nx + 1) return false;
-        for (int x0 = 0; x0 < a.nx; x0 += a.lx) {
-            const int xend = std::min(x0 + a.lx, a.nx);
-            const int c0 = std::max(x0 - H, 0), c1 = std::min(xend + H, a.nx);
-            if ((*hx)[c1] - (*hx)[c0] > cap) return false;
-        }
-        return true;
-    };
-    return fits(a.inj) && fits(a.rec);
+    return fits_chunks(c, k, a, a.inj) && fits_chunks(c, k, a, a.rec);
 }
 
 // A point table no chunk could stage: more than kPtsCap entries within some
@@ -1095,9 +1097,9 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // second-difference or imaging kernels follow (its own order); only
         // modes whose update itself needs the injected values fall back to the
         // untiled step
+        const bool imode = so.mode == kPlain || so.mode == kSaveD2 || so.mode == kImaging;
         const bool iheavy = heavy_table(c, a.inj);
-        const bool isep = iheavy && (so.mode == kPlain || so.mode == kSaveD2 || so.mode == kImaging);
-        if (c.plan.variant == FD_VARIANT_NAIVE || (iheavy && !isep)) {
+        if (c.plan.variant == FD_VARIANT_NAIVE || (iheavy && !imode)) {
             a.u0 = st.cur;
             a.um = st.prev;
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
@@ -1117,37 +1119,52 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             continue;
         }
         // receivers recorded after the pass need its output level in memory
-        const bool rsep = isep || heavy_table(c, a.rec);
-        const int T = (!rsep && nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+        bool isep = iheavy, rsep = iheavy || heavy_table(c, a.rec);
         const bool iso = c.base.w.iso != 0;
-        const int kmode = isep ? (int)kPlain : so.mode;
-        KernelKey k = (T == c.plan.key.T && kmode == kPlain) ? c.plan.key
-                                                              : key_for(c.plan.key, T, kmode, iso);
-        if (k.T != T) k = key_for(c.plan.key, 1, kmode, iso);
-        const int Tk = k.T;
-        a.u0 = st.cur;
-        a.um = st.prev;
-        float *o1, *o2 = nullptr;
-        if (Tk == 1) {
-            // in place: each point's u^{n-1} is read only by its owner (but a
-            // second difference saved after the pass needs u^{n-1} intact)
-            o1 = (isep && so.mode == kSaveD2) ? st.spare[0] : st.prev;
-        } else {
-            o1 = st.spare[0];
-            o2 = st.spare[1];
+        const SweepArgs a0 = a;
+        KernelKey k{};
+        float *o1 = nullptr, *o2 = nullptr;
+        auto plan_pass = [&]() {
+            a = a0;
+            const int T = (!rsep && nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+            const int kmode = isep ? (int)kPlain : so.mode;
+            k = (T == c.plan.key.T && kmode == kPlain) ? c.plan.key : key_for(c.plan.key, T, kmode, iso);
+            if (k.T != T) k = key_for(c.plan.key, 1, kmode, iso);
+            a.u0 = st.cur;
+            a.um = st.prev;
+            o2 = nullptr;
+            if (k.T == 1) {
+                // in place: each point's u^{n-1} is read only by its owner (but a
+                // second difference saved after the pass needs u^{n-1} intact)
+                o1 = (isep && so.mode == kSaveD2) ? st.spare[0] : st.prev;
+            } else {
+                o1 = st.spare[0];
+                o2 = st.spare[1];
+            }
+            a.o1 = o1;
+            a.o2 = o2;
+            a.lx = (k.T == c.plan.key.T && k.PY == c.plan.key.PY && k.NW == c.plan.key.NW)
+                       ? c.plan.lx
+                       : default_lx(d, k);
+            const int ty = stream_core_rows(k), tz = stream_core_cols(k);
+            a.ntz = (d.nz + tz - 1) / tz;
+            a.nty = (d.ny + ty - 1) / ty;
+            a.ntx = (d.nx + a.lx - 1) / a.lx;
+            a.remap = c.plan.remap ? 1 : 0;
+            a.alt = c.plan.alt ? 1 : 0;
+            a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
+        };
+        plan_pass();
+        // a table of more than a few entries that this pass's chunks cannot
+        // stage would be walked in memory one entry at a time: route it too
+        const bool ri = !isep && imode && a.inj.cnt > kStageMin && !fits_chunks(c, k, a, a.inj);
+        const bool rr = !rsep && a.rec.cnt > kStageMin && !fits_chunks(c, k, a, a.rec);
+        if (ri || rr) {
+            isep = isep || ri;
+            rsep = rsep || rr || isep;
+            plan_pass();
         }
-        a.o1 = o1;
-        a.o2 = o2;
-        a.lx = (k.T == c.plan.key.T && k.PY == c.plan.key.PY && k.NW == c.plan.key.NW)
-                   ? c.plan.lx
-                   : default_lx(d, k);
-        const int ty = stream_core_rows(k), tz = stream_core_cols(k);
-        a.ntz = (d.nz + tz - 1) / tz;
-        a.nty = (d.ny + ty - 1) / ty;
-        a.ntx = (d.nx + a.lx - 1) / a.lx;
-        a.remap = c.plan.remap ? 1 : 0;
-        a.alt = c.plan.alt ? 1 : 0;
-        a.ntl = stream_loads(c.plan.loads, resident_bytes(a, k.mode), k.T) ? 1 : 0;
+        const int Tk = k.T;
         const SweepArgs ar = a;
         if (rsep) a.rec = PointTable{};
         if (isep) a.inj = PointTable{};

@@ -193,3 +193,22 @@ def test_full_size_born_tiled_equals_untiled():
             for opt in (dict(variant=L.FD_VARIANT_NAIVE), bench.launch_options("cfg2"))]
     assert torch.equal(outs[0], outs[1])
     assert float(outs[1].abs().max()) > 0
+
+
+def test_tables_that_do_not_fit_long_chunks_equal_untiled():
+    """300 receivers between nodes along x: within any 32 planes they fit the
+    staging capacity, within the 128-plane chunks of a long-chunk launch they
+    do not, so those passes record them after the pass (and a time-blocked
+    request runs single levels); every form equals the untiled sweep and the
+    oracle."""
+    cs = make_case((160, 40, 64), 8, 40, 6, nsrc=1, nrec=4)
+    cs["src"] = np.array([[80.3, 19.6, 30.2]])
+    cs["rec"] = synth.offgrid_receiver_line(cs["shape"], 300, depth=30.4)
+    ref = oracle.forward(problem(cs), amp=cs["amp"].astype(np.float64))
+    base = gpu_fwd(cs, variant=L.FD_VARIANT_NAIVE)
+    assert rel_l2(base["rec"].cpu().numpy(), ref["rec"]) <= 1e-5
+    for o in (dict(variant=L.FD_VARIANT_STREAM, tile=(128, 32, 4)), dict(variant=L.FD_VARIANT_STREAM, tile=(32, 32, 4)),
+              dict(variant=L.FD_VARIANT_TBLOCK, tblock=2, tile=(128, 32, 4))):
+        out = gpu_fwd(cs, **o)
+        assert torch.equal(out["rec"], base["rec"]), o
+        assert torch.equal(out["u"], base["u"]), o
