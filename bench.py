@@ -51,7 +51,7 @@ def courant_max(so, ndim):
 
 
 def workload(name, device="cuda"):
-    """Synthetic workloads (recipes in the design doc).  Returns a dict of device inputs."""
+    """Seeded synthetic workloads (generators in synth/).  Returns a dict of device inputs."""
     import torch
 
     import synth

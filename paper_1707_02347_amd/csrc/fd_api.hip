@@ -1,5 +1,5 @@
 // fd_api.hip -- host side of libfdwave.so: validation, planning, workspace
-// layout, the sweep driver, checkpointed adjoint-state gradients, the
+// layout, the host sweep loop, checkpointed adjoint-state gradients, the
 // autotuner and the C ABI declared in include/fdwave.h.
 #include <hip/hip_runtime.h>
 
@@ -1019,7 +1019,7 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     return FD_OK;
 }
 
-// ------------------------------------------------------------------ the sweep driver
+// ------------------------------------------------------------------ the host sweep loop
 // State of a running sweep: (cur, prev) plus spare fields for ping-pong.
 struct State {
     float *cur, *prev;
