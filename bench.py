@@ -432,10 +432,11 @@ def main():
                     help="only the headline tiled sweep (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
-    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8", "born"], default=None,
+    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8", "born", "sinc"], default=None,
                     help="only 20-step sweeps of one more workload, for profiling runs: cfg3 "
-                         "(512^3 so 16, tiled), tblock-so8 (512^3 so 8, T = 1 then T = 2) or born "
-                         "(Born modelling on the headline grid, 256 receivers)")
+                         "(512^3 so 16, tiled), tblock-so8 (512^3 so 8, T = 1 then T = 2), born "
+                         "(Born modelling on the headline grid, 256 receivers) or sinc (the headline "
+                         "sweep with a windowed-sinc source and 256 windowed-sinc receivers, r = 4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -453,6 +454,16 @@ def main():
         ms = _timed(lambda: y.copy_(x), 5, 2)[0]
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return 0
+    if args.kernel_only == "sinc":
+        import synth
+
+        cs = offgrid(dict(workload("cfg2"), rec=synth.receiver_line((256,) * 3, 256, depth=20)))
+        cs = dict(cs, src=api.Sinc(cs["src"], 4), rec=api.Sinc(cs["rec"], 4))
+        for _ in range(args.warmup + args.steps):
+            _sweep(cs, launch_options("cfg2"), nt=20)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "sinc", "sweeps": args.warmup + args.steps, "steps": 20}), flush=True)
         return 0
     if args.kernel_only == "born":
         import synth
