@@ -913,6 +913,14 @@ bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
 // kernels follow.  Every route gives the same bits.
 constexpr int kHeavySpan = 32;
 
+// In a plain pass an injected table of more than this many entries is also
+// added after the pass (k_inject) rather than staged: on the 256^3 so-8 sweep
+// 64 / 256 multilinear sources ran at 309 / 210 GPts/s staged and 347 / 344
+// injected after the pass, one windowed-sinc source (512 nodes) 321 vs 351.
+// Modes that save second differences or image keep the staged walk, whose
+// alternative re-reads fields.
+constexpr int kRouteInjPlain = 256;
+
 bool heavy_table(const Ctx &c, const PointTable &t)
 {
     if (t.cnt <= kPtsCap) return false;
@@ -1157,7 +1165,8 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         plan_pass();
         // a table of more than a few entries that this pass's chunks cannot
         // stage would be walked in memory one entry at a time: route it too
-        const bool ri = !isep && imode && a.inj.cnt > kStageMin && !fits_chunks(c, k, a, a.inj);
+        const bool ri = !isep && imode && a.inj.cnt > kStageMin &&
+                        (!fits_chunks(c, k, a, a.inj) || (so.mode == kPlain && a.inj.cnt > kRouteInjPlain));
         const bool rr = !rsep && a.rec.cnt > kStageMin && !fits_chunks(c, k, a, a.rec);
         if (ri || rr) {
             isep = isep || ri;
