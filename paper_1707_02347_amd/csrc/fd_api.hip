@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1113,7 +1114,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             float *out = (so.mode == kSaveD2) ? st.spare[0] : st.prev;
             a.o1 = out;
             const int M = d.M, mode = so.mode;
-            float *cur = st.cur, *prev = st.prev, *d2 = a.d2 + a.dslot0 * d.Np;
+            float *cur = st.cur, *prev = st.prev, *d2 = a.d2 ? a.d2 + a.dslot0 * d.Np : nullptr;
             c.ex.call([a, M, out, cur, prev, d2, mode](hipStream_t s) {
                 hipError_t e = launch_naive_step(M, a, s);
                 if (e == hipSuccess) e = launch_inject(a, out, a.step0, s);
@@ -1183,7 +1184,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         if (rsep) {
             const int mode = so.mode;
             const float *cur = st.cur, *prev = st.prev;
-            float *d2 = a.d2 + a.dslot0 * d.Np;
+            float *d2 = a.d2 ? a.d2 + a.dslot0 * d.Np : nullptr;
             c.ex.call([ar, o1, cur, prev, d2, mode, isep](hipStream_t s) {
                 hipError_t e = isep ? launch_inject(ar, o1, ar.step0, s) : hipSuccess;
                 if (e == hipSuccess) e = launch_record(ar, o1, ar.step0, s);
@@ -2056,23 +2057,61 @@ void batch_chunk(Ctx &c, const fd_options &o)
 // same kernel configuration and Laplacian form become one grouped
 // launch over all their tiles, other ops run as recorded.  Shots are
 // independent, so any interleaving that keeps each shot's order is valid.
-// Streams and events of a batch's lanes, released on every exit path (a
-// stream or event still in use is released by the runtime once its work ends).
-struct LaneSet {
+// The lanes of a device: streams the library creates on first use and keeps
+// for the life of the process (as the runtime keeps its default stream), so a
+// batch never destroys a stream that may still hold its work, plus one private
+// stream per device for graph capture (the caller's may be the legacy default
+// stream, which cannot be captured).  A batch holds its device's pool for the
+// whole of its issue, so that batches issued from several host threads do not
+// interleave their fork and join events.
+struct LanePool {
+    std::mutex mu;
     std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;
-    ~LaneSet()
-    {
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
-        for (hipStream_t t : streams) (void)hipStreamDestroy(t);
+    hipStream_t capture = nullptr;
+};
+
+LanePool &lane_pool()
+{
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<LanePool>> pools;
+    int dev = 0;
+    FDW_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto &p = pools[dev];
+    if (!p) p.reset(new LanePool());
+    return *p;
+}
+
+void grow_lanes(LanePool &p, int n)
+{
+    while ((int)p.streams.size() < n) {
+        hipStream_t t = nullptr;
+        FDW_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        p.streams.push_back(t);
     }
-    hipEvent_t event()
+    if (!p.capture) FDW_HIP(hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking));
+}
+
+// Fork and join events of one batch, all created before any capture begins and
+// destroyed once the work that records or waits on them has completed (the
+// batch synchronises the caller's stream before it returns).
+struct LaneEvents {
+    std::vector<hipEvent_t> ev;
+    explicit LaneEvents(int n)
     {
-        hipEvent_t e = nullptr;
-        FDW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        events.push_back(e);
-        return e;
+        ev.reserve(n);
+        for (int i = 0; i < n; ++i) {
+            hipEvent_t e = nullptr;
+            FDW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            ev.push_back(e);
+        }
     }
+    ~LaneEvents()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    LaneEvents(const LaneEvents &) = delete;
+    LaneEvents &operator=(const LaneEvents &) = delete;
 };
 
 int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_lane,
@@ -2155,21 +2194,18 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_l
                                hipMemcpyHostToDevice, s));
     FDW_HIP(hipStreamSynchronize(s));
     const int nl = (int)lane_of.size();
-    LaneSet lanes;
-    for (int l = 0; nl > 1 && l < nl; ++l) {
-        hipStream_t t = nullptr;
-        FDW_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-        lanes.streams.push_back(t);
-    }
+    LanePool &pool = lane_pool();
+    std::lock_guard<std::mutex> lk(pool.mu);
+    grow_lanes(pool, nl > 1 ? nl : 0);
+    LaneEvents evs(nl > 1 ? nl + 1 : 0);  // fork, then one join per lane
     auto issue = [&](hipStream_t base) {
         if (nl > 1) {
-            hipEvent_t fork = lanes.event();
-            FDW_HIP(hipEventRecord(fork, base));
-            for (hipStream_t t : lanes.streams) FDW_HIP(hipStreamWaitEvent(t, fork, 0));
+            FDW_HIP(hipEventRecord(evs.ev[0], base));
+            for (int l = 0; l < nl; ++l) FDW_HIP(hipStreamWaitEvent(pool.streams[l], evs.ev[0], 0));
         }
         for (size_t li = 0; li < plan.size(); ++li) {
             const Launch &L = plan[li];
-            const hipStream_t st = nl > 1 ? lanes.streams[launch_lane[li]] : base;
+            const hipStream_t st = nl > 1 ? pool.streams[launch_lane[li]] : base;
             if (L.grouped) {
                 if (!launch_stream_grouped(L.key, L.iso, L.ntl, L.ps, dev_entries + L.off, L.n, L.total,
                                            L.grid, st))
@@ -2186,27 +2222,23 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_l
             }
         }
         if (nl > 1)
-            for (hipStream_t t : lanes.streams) {
-                hipEvent_t join = lanes.event();
-                FDW_HIP(hipEventRecord(join, t));
-                FDW_HIP(hipStreamWaitEvent(base, join, 0));
+            for (int l = 0; l < nl; ++l) {
+                FDW_HIP(hipEventRecord(evs.ev[1 + l], pool.streams[l]));
+                FDW_HIP(hipStreamWaitEvent(base, evs.ev[1 + l], 0));
             }
     };
     if (!graph) {
         issue(s);
+        // the fork and join events are destroyed on return: wait for the work
+        // that records them (the graph path below synchronises as well)
+        FDW_HIP(hipStreamSynchronize(s));
         return FD_OK;
     }
-    // capture on a private stream (the caller's may be the legacy default
-    // stream, which cannot be captured), replay on the caller's stream
-    hipStream_t cs = nullptr;
-    FDW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const hipStream_t cs = pool.capture;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        throw HipFail{e};
-    }
+    if (e != hipSuccess) throw HipFail{e};
     int status = FD_OK;
     try {
         issue(cs);
@@ -2222,7 +2254,6 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_l
     if (e == hipSuccess && status == FD_OK) e = hipStreamSynchronize(s);
     if (ge) (void)hipGraphExecDestroy(ge);
     if (g) (void)hipGraphDestroy(g);
-    (void)hipStreamDestroy(cs);
     if (status != FD_OK) return status;
     if (e != hipSuccess) throw HipFail{e};
     return FD_OK;
