@@ -294,11 +294,16 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
             size_t ws_bytes, const fd_options *opts, void *stream);
 
 /*
- * Autotuner: times candidate kernels (variant, tile, time-block depth) for a
+ * Autotuner, the counterpart of the auto-tuned spatial blocking that the
+ * paper's control runs use (Devito's block-size search, Sec. 6.6.1): times
+ * candidate kernels (variant, tile, time-block depth) for a
  * few steps at this grid's real shape (zero state, no points) on `stream`,
  * writes the fastest into *inout (fields left 0 are searched, set fields are
  * kept) and caches it in-process and, if the environment variable
- * FD_AUTOTUNE_CACHE names a file, in that file keyed by (ndim, n, so, arch).
+ * FD_AUTOTUNE_CACHE names a file, in that file keyed by (ndim, n, so, arch,
+ * Laplacian form: "iso" for equal spacing on every axis, else "aniso").
+ * Automatic plans (variant 0) of every operation on a grid with that key take
+ * the cached choice from then on.
  * Synchronises the stream.  workspace must hold
  * fd_workspace_size(grid, time, NULL, NULL, NULL, FD_OP_FORWARD) for time->nt = 8.
  */

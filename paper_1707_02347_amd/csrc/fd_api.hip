@@ -399,10 +399,16 @@ struct Plan {
 std::mutex g_tune_mu;
 std::map<std::string, fd_options> g_tune;
 
+// Key of a tuned choice: grid extents, space order, the architecture and the
+// Laplacian's form (equal spacing on every axis, or not: the two forms compile
+// to different kernels, and the tuner times the grid's own).  The tuner
+// times plain forward passes; the other operations run the same tile (their
+// modes' kernels are compiled for the shapes the tuner searches).
 std::string tune_key(const Dims &d)
 {
     char buf[128];
-    std::snprintf(buf, sizeof buf, "%d %d %d %d %d gfx950", d.ndim, d.nx, d.ny, d.nz, 2 * d.M);
+    std::snprintf(buf, sizeof buf, "%d %d %d %d %d gfx950 %s", d.ndim, d.nx, d.ny, d.nz, 2 * d.M,
+                  grid_iso(d) ? "iso" : "aniso");
     return buf;
 }
 
@@ -418,11 +424,11 @@ void load_tune_file()
     char line[256];
     while (std::fgets(line, sizeof line, f)) {
         int nd, nx, ny, nz, so, var, t0, t1, t2, tb;
-        char arch[32];
-        if (std::sscanf(line, "%d %d %d %d %d %31s %d %d %d %d %d", &nd, &nx, &ny, &nz, &so, arch,
-                        &var, &t0, &t1, &t2, &tb) == 11) {
+        char arch[32], form[8];
+        if (std::sscanf(line, "%d %d %d %d %d %31s %7s %d %d %d %d %d", &nd, &nx, &ny, &nz, &so, arch, form,
+                        &var, &t0, &t1, &t2, &tb) == 12) {
             char key[128];
-            std::snprintf(key, sizeof key, "%d %d %d %d %d %s", nd, nx, ny, nz, so, arch);
+            std::snprintf(key, sizeof key, "%d %d %d %d %d %s %s", nd, nx, ny, nz, so, arch, form);
             fd_options o{};
             o.variant = var;
             o.tile[0] = t0;
@@ -515,7 +521,15 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
         auto it = g_tune.find(tune_key(d));
-        if (it != g_tune.end()) {
+        // a cached choice whose kernel this grid's form lacks is ignored
+        const bool usable =
+            it != g_tune.end() &&
+            (it->second.variant == FD_VARIANT_NAIVE ||
+             (it->second.tile[2] > 0 && it->second.tile[1] % it->second.tile[2] == 0 &&
+              stream_has(KernelKey{d.M, std::max(it->second.tblock, 1), it->second.tile[2],
+                                   it->second.tile[1] / it->second.tile[2], kPlain},
+                         grid_iso(d))));
+        if (usable) {
             const fd_options &t = it->second;
             eff.variant = t.variant;
             for (int i = 0; i < 3; ++i)
@@ -875,6 +889,7 @@ struct Ctx {
     Layout L;
     SweepArgs base;   // common launch arguments
     std::vector<int32_t> hxs, hxr;  // host copies of the point tables' plane pointers
+    int ran_T = 0;    // deepest time block a pass of this call used (0: none yet)
 };
 
 // Whether a pass walks its point entries staged in LDS: a configuration that
@@ -914,12 +929,13 @@ bool stage_points(const Ctx &c, const KernelKey &k, const SweepArgs &a)
 // kernels follow.  Every route gives the same bits.
 constexpr int kHeavySpan = 32;
 
-// In a plain pass an injected table of more than this many entries is also
-// added after the pass (k_inject) rather than staged: on the 256^3 so-8 sweep
-// 64 / 256 multilinear sources ran at 309 / 210 GPts/s staged and 347 / 344
-// injected after the pass, one windowed-sinc source (512 nodes) 321 vs 351.
-// Modes that save second differences or image keep the staged walk, whose
-// alternative re-reads fields.
+// In a plain single-level pass an injected table of more than this many
+// entries is also added after the pass (k_inject) rather than staged: on the
+// 256^3 so-8 sweep 64 / 256 multilinear sources ran at 309 / 210 GPts/s staged
+// and 347 / 344 injected after the pass, one windowed-sinc source (512 nodes)
+// 321 vs 351.  Time-blocked passes keep staging such tables (routing them out
+// would drop the pass to one level), and so do the modes that save second
+// differences or image, whose alternative re-reads fields.
 constexpr int kRouteInjPlain = 256;
 
 bool heavy_table(const Ctx &c, const PointTable &t)
@@ -1167,7 +1183,8 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // a table of more than a few entries that this pass's chunks cannot
         // stage would be walked in memory one entry at a time: route it too
         const bool ri = !isep && imode && a.inj.cnt > kStageMin &&
-                        (!fits_chunks(c, k, a, a.inj) || (so.mode == kPlain && a.inj.cnt > kRouteInjPlain));
+                        (!fits_chunks(c, k, a, a.inj) ||
+                         (so.mode == kPlain && k.T == 1 && a.inj.cnt > kRouteInjPlain));
         const bool rr = !rsep && a.rec.cnt > kStageMin && !fits_chunks(c, k, a, a.rec);
         if (ri || rr) {
             isep = isep || ri;
@@ -1195,6 +1212,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         }
         if (Tk == 1) swap_in(st, o1, st.cur);
         else swap_in(st, o1, o2);
+        c.ran_T = std::max(c.ran_T, Tk);
         s += Tk;
     }
 }
@@ -1226,6 +1244,7 @@ void born_fused_step(Ctx &c, State &sb, State &sp, int64_t step, const KernelKey
     a.ps = stage_points(c, k, a) ? 1 : 0;
     supertile(k, a);
     c.ex.pass(k, a, c.plan.loads);
+    c.ran_T = std::max(c.ran_T, 1);
     std::swap(sb.cur, sb.prev);
     std::swap(sp.cur, sp.prev);
 }
@@ -1249,14 +1268,19 @@ void place_state(const State &st, float *A, float *B, float *tmp, int64_t N, hip
     }
 }
 
-void record_last(const Plan &p)
+// The configuration of the last call: its plan, with the time-block depth the
+// passes actually used (a route for large point tables or a short tail of
+// steps can run fewer levels than planned).
+void record_last(const Ctx &c)
 {
+    const Plan &p = c.plan;
     g_last = fd_options{};
     g_last.variant = p.variant;
     g_last.tile[0] = p.lx;
     g_last.tile[1] = p.key.NW * p.key.PY;
     g_last.tile[2] = p.key.PY;
-    g_last.tblock = p.key.T;
+    g_last.tblock = c.ran_T > 0 ? c.ran_T : p.key.T;
+    if (p.variant == FD_VARIANT_TBLOCK && c.ran_T == 1) g_last.variant = FD_VARIANT_STREAM;
     g_last_valid = true;
 }
 
@@ -1499,7 +1523,7 @@ int fd_forward(const fd_grid *grid, const fd_time *time, const float *v, const f
                            stream);
         if (rc) return rc;
         fwd_issue(j);
-        record_last(j.c.plan);
+        record_last(j.c);
         if (j.flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, j.c.nt * j.nr, j.c.s);
         return FD_OK;
     });
@@ -1553,7 +1577,7 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
             FDW_HIP(launch_repitch(lam_state, c.d.nz, st.cur, c.d.nzp, rows, c.d.nz, c.s));
             FDW_HIP(launch_repitch(lam_state + c.d.N, c.d.nz, st.prev, c.d.nzp, rows, c.d.nz, c.s));
         }
-        record_last(c.plan);
+        record_last(c);
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(src_out, c.nt * ns, c.s);
         return FD_OK;
     });
@@ -1629,7 +1653,7 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
             }
         }
         gather_traces(c, c.L.rec, nr, pb.rec.cnt, rec_out, 1.0f);
-        record_last(c.plan);
+        record_last(c);
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, c.nt * nr, c.s);
         return FD_OK;
     });
@@ -1830,7 +1854,7 @@ int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, cons
     if (rc) return rc;
     grad_issue(j);
     if (!y && misfit) *misfit = grad_misfit(j);
-    record_last(j.c.plan);
+    record_last(j.c);
     return FD_OK;
 }
 
@@ -1983,9 +2007,17 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         a.rec = as_table(c.L.rec, 0, 0, false);
         a.rscale = 1.0f;
         a.adir = a.rdir = 1;
-        hipEvent_t e0, e1;
-        FDW_HIP(hipEventCreate(&e0));
-        FDW_HIP(hipEventCreate(&e1));
+        struct Events {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~Events()
+            {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
+        } ev;
+        FDW_HIP(hipEventCreate(&ev.e0));
+        FDW_HIP(hipEventCreate(&ev.e1));
+        const hipEvent_t e0 = ev.e0, e1 = ev.e1;
         float best = 1e30f;
         fd_options best_o = fixed;
         bool found = false;
@@ -2016,8 +2048,6 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
                 found = true;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         if (!found) return FD_EUNSUPPORTED;
         *inout = best_o;
         {

@@ -47,10 +47,15 @@ def test_tuned_configuration_is_exact_and_used_by_automatic_plans(tmp_path, monk
     if tuned["variant"] != L.FD_VARIANT_NAIVE:
         assert tuple(cfg["tile"]) == tuple(tuned["tile"])
     assert torch.equal(auto["rec"], base["rec"])
-    # the choice is appended to the cache file, keyed by (ndim, n, so, arch)
+    # the choice is appended to the cache file, keyed by (ndim, n, so, arch, Laplacian form)
     line = cache.read_text().strip().splitlines()[-1].split()
-    assert [int(x) for x in line[:5]] == [3, *v.shape, so] and line[5] == "gfx950"
-    assert int(line[6]) == tuned["variant"]
+    assert [int(x) for x in line[:5]] == [3, *v.shape, so] and line[5] == "gfx950" and line[6] == "iso"
+    assert int(line[7]) == tuned["variant"]
+    # an anisotropic grid of the same shape does not take the equal-spacing choice
+    h2 = [10.0, 12.5, 10.0]
+    base2 = run(v, h2, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
+    auto2 = run(v, h2, so, nt, dt, src, rec, amp)
+    assert torch.equal(auto2["rec"], base2["rec"])
 
 
 def test_tuner_keeps_fixed_fields():

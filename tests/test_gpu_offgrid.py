@@ -235,3 +235,21 @@ def test_many_sources_injected_after_plain_passes_equal_untiled():
     J0, g0, _ = api.gradient(*args, sponge=cs["sponge"], vref=cs["vref"], variant=L.FD_VARIANT_NAIVE, ckpt_every=16)
     J1, g1, _ = api.gradient(*args, sponge=cs["sponge"], vref=cs["vref"], variant=L.FD_VARIANT_STREAM, ckpt_every=16)
     assert J0 == J1 and torch.equal(g0, g1)
+
+
+def test_many_sources_keep_the_time_block():
+    """More than 256 injected entries that every chunk can stage: a time-blocked
+    plan keeps T = 2 with the entries staged inside the time tile (a single-level
+    plan adds such tables after the pass instead), equal to the untiled kernel
+    bit for bit and to the oracle within 1e-5."""
+    shape, so, nt = (96, 40, 48), 4, 60
+    cs = make_case(shape, so, nt, 5, nsrc=40, nrec=9)
+    cs["src"] = synth.offgrid_points(shape, 40, seed=77, margin=1.0)  # 40 x 8 = 320 entries
+    base = gpu_fwd(cs, variant=L.FD_VARIANT_NAIVE)
+    tb = gpu_fwd(cs, variant=L.FD_VARIANT_TBLOCK, tblock=2, tile=(12, 32, 4))
+    cfg = api.last_config()
+    assert cfg["tblock"] == 2 and cfg["variant"] == L.FD_VARIANT_TBLOCK, cfg
+    assert torch.equal(tb["rec"], base["rec"]) and torch.equal(tb["u"], base["u"])
+    ref = oracle.forward(problem(cs), amp=cs["amp"].astype(np.float64))
+    assert rel_l2(tb["u"].cpu().numpy(), ref["u"]) <= 1e-5
+    assert rel_l2(tb["rec"].cpu().numpy(), ref["rec"]) <= 1e-5
