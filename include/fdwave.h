@@ -94,6 +94,8 @@ extern "C" {
 #define FD_ENONFINITE (-7)    /* v has a NaN/Inf/non-positive entry, or (with
                                  FD_FLAG_CHECK_FINITE) the traces are not finite */
 #define FD_EUNSUPPORTED (-8)  /* no compiled kernel for the requested options */
+#define FD_ESCRATCH (-9)      /* fd_forward_noalloc: the call needs more scratch than
+                                 FD_NOALLOC_SCRATCH_BYTES */
 
 /* ------------------------------------------------------------------ variants */
 #define FD_VARIANT_AUTO 0    /* autotuner / cached choice */
@@ -309,6 +311,26 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
  */
 int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options *inout, void *workspace,
                 size_t ws_bytes, void *stream);
+
+/*
+ * fd_forward without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results and errors as fd_forward; the scratch that
+ * fd_forward carves from the caller's workspace (q, the spare fields, the point
+ * tables) lives instead in a static device array of FD_NOALLOC_SCRATCH_BYTES
+ * that every GPU the library runs on holds until the process ends.  The call
+ * allocates nothing: it returns FD_ESCRATCH when
+ * fd_workspace_size(grid, time, src, rec, opts, FD_OP_FORWARD) exceeds the
+ * array (64 MiB: a 3-D grid of about 2.4e6 points with nz a multiple of 32, a
+ * 2-D grid of 128 x 128 easily).  Every call on one GPU uses that GPU's one
+ * array, which keeps the last call's contents (each call writes everything it
+ * reads): calls that overlap on one GPU, on different streams or host
+ * threads, race and must be serialised by the caller.
+ */
+#define FD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fd_forward_noalloc(const fd_grid *grid, const fd_time *time, const float *v,
+                       const fd_points *src, const fd_points *rec, float *rec_out,
+                       float *u_state, const fd_options *opts, void *stream);
 
 /* One shot of a batch (all pointers as in fd_forward / fd_gradient). */
 typedef struct fd_shot {

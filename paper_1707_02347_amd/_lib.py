@@ -24,6 +24,9 @@ FD_ENOMEM = -5
 FD_EHIP = -6
 FD_ENONFINITE = -7
 FD_EUNSUPPORTED = -8
+FD_ESCRATCH = -9
+
+FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 FD_VARIANT_AUTO = 0
 FD_VARIANT_NAIVE = 1
@@ -114,6 +117,9 @@ SYMBOLS = {
     "fd_forward": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.POINTER(fd_points),
                              C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                              C.POINTER(fd_options), C.c_void_p]),
+    "fd_forward_noalloc": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.POINTER(fd_points),
+                                     C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.POINTER(fd_options),
+                                     C.c_void_p]),
     "fd_adjoint": (C.c_int, [C.POINTER(fd_grid), C.POINTER(fd_time), C.c_void_p, C.POINTER(fd_points),
                              C.POINTER(fd_points), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                              C.POINTER(fd_options), C.c_void_p]),
@@ -175,6 +181,10 @@ def fd_gradient_storage(grid, time, src, rec, op, budget, inout, ws_bytes):
 
 def fd_forward(grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts, stream):
     return load().fd_forward(grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts, stream)
+
+
+def fd_forward_noalloc(grid, time, v, src, rec, rec_out, u_state, opts, stream):
+    return load().fd_forward_noalloc(grid, time, v, src, rec, rec_out, u_state, opts, stream)
 
 
 def fd_adjoint(grid, time, v, src, rec, src_out, lam_state, workspace, ws_bytes, opts, stream):

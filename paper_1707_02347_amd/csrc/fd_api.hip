@@ -1432,6 +1432,44 @@ void fwd_issue(FwdJob &j)
     }
 }
 
+int forward_impl(const fd_grid *grid, const fd_time *time, const float *v, const fd_points *src,
+                 const fd_points *rec, float *rec_out, float *u_state, void *workspace,
+                 size_t ws_bytes, const fd_options *opts, void *stream)
+{
+    FwdJob j;
+    int rc = fwd_setup(j, grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts, stream);
+    if (rc) return rc;
+    fwd_issue(j);
+    record_last(j.c);
+    if (j.flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, j.c.nt * j.nr, j.c.s);
+    return FD_OK;
+}
+
+// Scratch of fd_forward_noalloc: a forward call's workspace in a static device
+// array.  Each device holds its own copy; host code reaches it only through
+// the device address hipGetSymbolAddress returns (the array's name is a host
+// stand-in, not a device address), looked up once per device.
+constexpr size_t kScratchBytes = FD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void *scratch_ptr()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *ptrs[kMaxDevices] = {};
+    int dev = 0;
+    FDW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Status{FD_EINVAL};
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        FDW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) throw HipFail{hipErrorInvalidSymbol};
+        ptrs[dev] = p;
+    }
+    return ptrs[dev];
+}
+
 }  // namespace fdw
 
 using namespace fdw;
@@ -1451,6 +1489,7 @@ const char *fd_strerror(int code)
     case FD_EHIP: return "HIP runtime error";
     case FD_ENONFINITE: return "non-finite or non-positive values";
     case FD_EUNSUPPORTED: return "no compiled kernel for the requested options";
+    case FD_ESCRATCH: return "the call needs more scratch than the library's static array holds";
     default: return "unknown status";
     }
 }
@@ -1518,14 +1557,20 @@ int fd_forward(const fd_grid *grid, const fd_time *time, const float *v, const f
                size_t ws_bytes, const fd_options *opts, void *stream)
 {
     return guarded([&]() -> int {
-        FwdJob j;
-        int rc = fwd_setup(j, grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts,
-                           stream);
-        if (rc) return rc;
-        fwd_issue(j);
-        record_last(j.c);
-        if (j.flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, j.c.nt * j.nr, j.c.s);
-        return FD_OK;
+        return forward_impl(grid, time, v, src, rec, rec_out, u_state, workspace, ws_bytes, opts, stream);
+    });
+}
+
+int fd_forward_noalloc(const fd_grid *grid, const fd_time *time, const float *v,
+                       const fd_points *src, const fd_points *rec, float *rec_out,
+                       float *u_state, const fd_options *opts, void *stream)
+{
+    return guarded([&]() -> int {
+        const size_t need = fd_workspace_size(grid, time, src, rec, opts, FD_OP_FORWARD);
+        if (!need) return FD_EINVAL;
+        if (need > kScratchBytes) return FD_ESCRATCH;
+        return forward_impl(grid, time, v, src, rec, rec_out, u_state, scratch_ptr(), kScratchBytes, opts,
+                            stream);
     });
 }
 

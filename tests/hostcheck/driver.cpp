@@ -215,6 +215,18 @@ void born_case(const std::string &name, const fd_grid &g, int64_t nt, Pts src, P
     expect(fd_born(&g, &t, v.f(), dv.f(), &src.p, &rec.p, out.f(), w.p, ws, &o, nullptr), FD_OK, "born " + name);
 }
 
+void noalloc_case(const std::string &name, const fd_grid &g, int64_t nt, Pts src, Pts rec, fd_options o, int want)
+{
+    const fd_time t{nt, stable_dt(g)};
+    const int64_t N = points(g);
+    Buf v(N * 4), amp((size_t)std::max<int64_t>(nt, 1) * std::max(src.p.n, 1) * 4);
+    Buf out((size_t)std::max<int64_t>(nt, 1) * std::max(rec.p.n, 1) * 4), st(2 * N * 4);
+    for (int64_t i = 0; i < N; ++i) v.f()[i] = 2000.0f;
+    src.p.amp = amp.f();
+    expect(fd_forward_noalloc(&g, &t, v.f(), &src.p, &rec.p, rec.p.n ? out.f() : nullptr, st.f(), &o, nullptr), want,
+           "forward without allocation " + name);
+}
+
 // ---------------------------------------------------------------- batches
 struct ShotSpec {
     std::vector<int> n;
@@ -311,6 +323,13 @@ int main()
     forward_case("sinc source and receivers", g3, 20, scattered(g3, 1, 4, 5), scattered(g3, 30, 4, 6),
                  opts(FD_VARIANT_STREAM), false);
     forward_case("sinc 2-D", g2, 20, scattered(g2, 2, 3, 7), scattered(g2, 20, 8, 8), opts(), false);
+    // the entry point without a workspace: twice, then a grid beyond its scratch
+    noalloc_case("so8", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM), FD_OK);
+    noalloc_case("so4 smaller", g4, 20, centre_src(g4, 15), rec_line(g4, 7, 15), opts(), FD_OK);
+    {
+        const fd_grid big = grid({160, 160, 160}, 8);
+        noalloc_case("too large", big, 4, centre_src(big, 12), Pts(), opts(), FD_ESCRATCH);
+    }
     // adjoint, gradients (checkpointed and whole time axis), vjp, Born
     adjoint_case("so8", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM));
     adjoint_case("so4 T2 offgrid", g4, 24, scattered(g4, 2, 0, 9), scattered(g4, 30, 0, 10),

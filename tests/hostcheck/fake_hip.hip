@@ -367,7 +367,27 @@ void __hipRegisterFunction(void **, const void *host, char *, const char *dev_na
     parse_template(k);
     kernels()[host] = k;
 }
-void __hipRegisterVar(void **, void *, char *, const char *, int, size_t, int, int) {}
+// device variables: their host shadows stand in for the device copies
+std::map<const void *, size_t> &vars()
+{
+    static std::map<const void *, size_t> *m = new std::map<const void *, size_t>();
+    return *m;
+}
+void __hipRegisterVar(void **, void *var, char *, const char *, int, size_t size, int, int)
+{
+    vars()[var] = size;
+}
+hipError_t hipGetSymbolAddress(void **p, const void *symbol)
+{
+    auto it = vars().find(symbol);
+    if (it == vars().end()) {
+        fail("address of an unregistered device symbol");
+        return hipErrorInvalidSymbol;
+    }
+    g_alloc[(uintptr_t)symbol] = it->second;
+    *p = const_cast<void *>(symbol);
+    return hipSuccess;
+}
 
 hipError_t __hipPushCallConfiguration(dim3 grid, dim3 block, size_t shm, hipStream_t s)
 {
