@@ -1,16 +1,24 @@
 """Benchmark of the acoustic FD sweep on one MI355X.
 
-One "step" of this benchmark is one whole forward sweep of the headline
-workload: 3-D 256^3 grid, space order 8, 500 time steps, smoothed random
+One "step" of this benchmark is one whole forward sweep of the large
+workload: 3-D 512^3 grid, space order 16, 1000 time steps, smoothed random
 velocity (seed 1707, sigma 8 cells, 1.5-4.5 km/s), 15 Hz Ricker source at
-depth 20, 20-cell sponge, time-tiled kernel, all inputs resident in HBM.
-``value`` is GPts/s = N^3 * nt / t_sweep.  Next to it the line reports the
-untiled and space-tiled kernels on the same workload, the 512^3 space-order-16
-sweep (tiled vs untiled), FWI gradients/s (256^3, 1000 steps, 256 receivers,
-checkpoint every 50), the batched shots, the dominant kernel's HBM roofline
-and the FP64 oracle timed on the host cores.
+depth 20, 40-cell sponge, tiled kernel, all inputs resident in HBM.  Its three
+512 MiB fields are far beyond the 256 MB Infinity Cache, so the sweep is bound
+by HBM.  ``value`` is GPts/s = 512^3 * 1000 / t_sweep.  Next to it the line
+reports the untiled and time-blocked kernels on the same workload, the tiled
+adjoint sweep, the 256^3 space-order-8 sweep (three 64 MiB fields: resident in
+the Infinity Cache, reported as such), FWI gradients/s (256^3, 1000 steps,
+256 receivers, checkpoint every 50), the batched shots, the dominant kernel's
+HBM roofline and the FP64 oracle timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-oracle]
+Kernel configurations come from the library's autotuner (fd_autotune): its
+choices for these workloads, made on an MI355X with ``--retune``, are kept in
+paper_1707_02347_amd/autotune_gfx950.txt, which the library reads as its tuning
+cache (FD_AUTOTUNE_CACHE); every sweep below asks for the automatic
+configuration and records the one that ran.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-oracle] [--retune PATH]
 """
 from __future__ import annotations
 
@@ -26,6 +34,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
+TUNE_CACHE = os.path.join(HERE, "paper_1707_02347_amd", "autotune_gfx950.txt")
 
 METRIC = "GPts/s + % HBM roofline, tiled vs untiled; FWI gradients/s at rel err 1e-5"
 HBM_PEAK_GBS = 8000.0
@@ -80,21 +89,39 @@ def workload(name, device="cuda"):
                 amp=torch.from_numpy(amp).to(device), rec=rec, sponge=L, vref=4500.0)
 
 
-# Launch configurations (tile = (planes per workgroup along x, tile rows,
-# rows per thread)), chosen from MI355X sweeps of the library's autotuner search
-# space: for these workloads the space-tiled kernel (T = 1) is the fastest;
-# the time-blocked T = 2 kernel is reported beside it.
-TUNED = {
-    "cfg2": dict(variant=2, tile=(32, 32, 4)),
-    "cfg2_t2": dict(variant=3, tblock=2, tile=(64, 32, 2)),
-    "cfg3": dict(variant=2, tile=(128, 16, 4)),
-    "cfg3_t2": dict(variant=3, tblock=2, tile=(64, 32, 4)),
-    "cfg4": dict(variant=2, tile=(32, 32, 4)),
-}
+AUTO = dict(variant=0)  # the autotuner's cached choice for the grid (space-tiled default if none)
+T2 = dict(variant=3, tblock=2)  # time-blocked, two levels per pass, default tile
 
 
 def launch_options(name):
-    return dict(TUNED.get(name, dict(variant=2)))
+    """Options of a workload's tiled sweep: automatic, i.e. the autotuner's choice."""
+    return dict(AUTO)
+
+
+def retune(path):
+    """Run fd_autotune on every workload shape of this benchmark and write the
+    choices to ``path`` (the library appends each choice to FD_AUTOTUNE_CACHE)."""
+    import torch
+
+    from paper_1707_02347_amd import api
+
+    if os.path.exists(path):
+        os.remove(path)
+    os.environ["FD_AUTOTUNE_CACHE"] = path
+    dt_of = lambda so: 0.8 * courant_max(so, 3) * 10.0 / 4500.0  # the workloads' time step
+    # the single-shot workloads (the 256^3 grid serves the sweep, gradient, Born
+    # and off-grid rates); batches are tuned per space-order class by
+    # fd_batch_autotune instead, since shots tuned one by one would split the
+    # grouped launches
+    shapes = {((512,) * 3, 16): (dt_of(16), 40), ((256,) * 3, 8): (dt_of(8), 20)}
+    out = {}
+    for (shape, so), (dt, sponge) in shapes.items():
+        t0 = time.perf_counter()
+        o = api.autotune(shape, [10.0] * 3, so, dt, sponge=sponge, vref=4500.0, nt=32)
+        out[f"{shape[0]}^3 so{so}"] = dict(o, seconds=round(time.perf_counter() - t0, 2))
+        print(f"# tuned {shape} so{so}: {o}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return out
 
 
 def kernel_source_hash():
@@ -107,10 +134,11 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the headline kernel from the committed rocprofv3
-    counter summary, if it was taken with the current kernel source."""
-    path = os.path.join(HERE, "profiles", "k_stream_cfg2_counters.txt")
+def profiled_traffic(profile, kernel):
+    """HBM bytes per launch of ``kernel`` from a committed rocprofv3 counter
+    summary under profiles/, if it was taken with the current kernel source
+    and for that kernel configuration (else None)."""
+    path = os.path.join(HERE, "profiles", profile)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -118,12 +146,19 @@ def profiled_traffic():
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
+    if kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def kernel_name(cfg, so):
+    """Template name of the sweep kernel a configuration (fd_last_config) runs."""
+    PY = int(cfg["tile"][2])
+    NW = int(cfg["tile"][1]) // max(PY, 1)
+    return f"k_stream<M={so // 2},T={int(cfg['tblock'])},PY={PY},NW={NW}>"
 
 
 def _sweep(cs, opts, nt=None):
@@ -185,6 +220,42 @@ def streaming_ceiling(field_mib, reps=30):
 def time_sweeps(cs, opts, steps, warmup):
     """Median / mean / std ms of whole sweeps (HIP events on the launch stream)."""
     return _timed(lambda: _sweep(cs, opts), steps, warmup)
+
+
+def adjoint_case(cs, nrec=256):
+    """The adjoint sweep of a workload: residual traces injected at ``nrec``
+    receivers on a line at depth 20 (seeded synthetic traces), the result
+    recorded at the source."""
+    import torch
+
+    import synth
+
+    rec = synth.receiver_line(cs["v"].shape, nrec, depth=20)
+    g = torch.Generator(device=cs["v"].device).manual_seed(2347)
+    res = torch.randn((cs["nt"], nrec), generator=g, device=cs["v"].device) * cs["amp"].abs().max()
+    return rec, res
+
+
+def _adjoint(cs, rec, res, opts, nt=None):
+    from paper_1707_02347_amd import api
+
+    n = cs["nt"] if nt is None else nt
+    return api.adjoint(cs["v"], cs["h"], cs["so"], n, cs["dt"], cs["src"], rec, res[: max(n, 0)].contiguous(),
+                       sponge=cs["sponge"], vref=cs["vref"], **opts)
+
+
+def roofline_of(sweep_ms, setup, launches, npts, bytes_per_point, kernel, profile=None):
+    """Roofline block of a sweep's dominant kernel: its average launch time
+    (sweep minus a zero-step call with the same set-up, over the launches) and
+    the algorithmic bytes per launch."""
+    kern_ms = max(sweep_ms - setup, 1e-6) / launches
+    bpl = bytes_per_point * npts
+    achieved = bpl / (kern_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic(profile, kernel) if profile else None,
+            "kernel": kernel, "avg_launch_us": round(kern_ms * 1e3, 2), "launches": launches,
+            "bytes_per_launch": bpl, "bytes_per_point": bytes_per_point}
 
 
 def time_block(fn, steps, warmup):
@@ -380,7 +451,7 @@ def batch_shots(device="cuda"):
         amp = torch.from_numpy(synth.ricker(nt, dt, 15.0)[:, None].copy()).to(device)
         shots.append(dict(v=v, h=[10.0] * 3, so=so, nt=nt, dt=dt, src_idx=synth.centre_source(shape, depth=20),
                           src_amp=amp, rec_idx=synth.receiver_line(shape, 128, depth=20), sponge=20, vref=4500.0,
-                          options=dict(variant=2, ckpt_every=50)))
+                          options=dict(launch_options("cfg5"), ckpt_every=50)))
     return shots
 
 
@@ -394,6 +465,16 @@ def batch_rates():
     shots = batch_shots()
     pts = sum(float(np.prod(s["v"].shape)) * s["nt"] for s in shots)
     res = {}
+    # the planner's default tile for every shot, then the batch tuner's choice
+    # (one kernel per space-order class, timed on the class's grouped launches)
+    dflt = [dict(s, options=dict(s["options"], variant=2)) for s in shots]
+    med_d, _, _ = _timed(lambda: api.forward_batch(dflt, graph=True), 1, 1)
+    res["forward_batched_default_tile_gpts"] = round(pts / (med_d * 1e-3) / 1e9, 2)
+    del dflt
+    t0 = time.perf_counter()
+    chosen = api.batch_autotune(shots)
+    res["batch_autotune_s"] = round(time.perf_counter() - t0, 2)
+    res["batch_autotune_choice"] = {f"so{s['so']}": c for s, c in zip(shots, chosen)}
     med, _, _ = _timed(lambda: api.forward_batch(shots, graph=True), 1, 1)
     res["forward_batched_gpts"] = round(pts / (med * 1e-3) / 1e9, 2)
 
@@ -428,20 +509,27 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-oracle", action="store_true")
-    ap.add_argument("--headline-only-kernel", action="store_true",
-                    help="only the headline tiled sweep (for profiling runs)")
+    ap.add_argument("--retune", metavar="PATH", default=None,
+                    help="run the autotuner on every workload shape and write its choices to PATH")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
-    ap.add_argument("--kernel-only", choices=["cfg3", "tblock-so8", "born", "sinc"], default=None,
-                    help="only 20-step sweeps of one more workload, for profiling runs: cfg3 "
-                         "(512^3 so 16, tiled), tblock-so8 (512^3 so 8, T = 1 then T = 2), born "
-                         "(Born modelling on the headline grid, 256 receivers) or sinc (the headline "
-                         "sweep with a windowed-sinc source and 256 windowed-sinc receivers, r = 4)")
+    ap.add_argument("--kernel-only", choices=["cfg3", "cfg3-adjoint", "cfg2", "tblock-so8", "born", "sinc", "batch"],
+                    default=None,
+                    help="only short runs of one workload, for profiling: cfg3 (512^3 so 16, whole "
+                         "sweeps), cfg3-adjoint (its adjoint, whole sweeps), cfg2 (256^3 so 8, whole "
+                         "sweeps), tblock-so8 (512^3 so 8, T = 1 then T = 2), born (Born modelling "
+                         "on the 256^3 grid, 256 receivers), sinc (the 256^3 sweep with windowed-sinc "
+                         "points, r = 4) or batch (the 32-shot forward batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         return 2
+    if args.retune:
+        print(json.dumps({"retuned": retune(args.retune), "cache": args.retune}), flush=True)
+        return 0
+    # the autotuner's cached choices: automatic plans of these grids take them
+    os.environ.setdefault("FD_AUTOTUNE_CACHE", TUNE_CACHE)
 
     import torch
 
@@ -455,122 +543,99 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return 0
-    if args.kernel_only == "sinc":
-        import synth
-
-        cs = offgrid(dict(workload("cfg2"), rec=synth.receiver_line((256,) * 3, 256, depth=20)))
-        cs = dict(cs, src=api.Sinc(cs["src"], 4), rec=api.Sinc(cs["rec"], 4))
-        for _ in range(args.warmup + args.steps):
-            _sweep(cs, launch_options("cfg2"), nt=20)
-        torch.cuda.synchronize()
-        print(json.dumps({"profiled": "sinc", "sweeps": args.warmup + args.steps, "steps": 20}), flush=True)
-        return 0
-    if args.kernel_only == "born":
-        import synth
-
-        cs = workload("cfg2")
-        rec = synth.receiver_line(cs["v"].shape, 256, depth=20)
-        dv = 0.05 * (synth.blob_velocity(cs["v"], amp=1.0, width_frac=1.0 / 16.0) - cs["v"])
-        for _ in range(args.warmup + args.steps):
-            api.born(cs["v"], cs["h"], cs["so"], 20, cs["dt"], cs["src"], cs["amp"][:20].contiguous(), rec, dv,
-                     sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg2"))
-        torch.cuda.synchronize()
-        print(json.dumps({"profiled": "born", "runs": args.warmup + args.steps, "steps": 20}), flush=True)
-        return 0
     if args.kernel_only:
-        import synth
+        return kernel_only(args)
 
-        cs = workload("cfg3")
-        opts = [launch_options("cfg3")]
-        if args.kernel_only == "tblock-so8":
-            cs["so"] = 8
-            cs["dt"] = 0.8 * courant_max(8, 3) * 10.0 / 4500.0
-            cs["amp"] = torch.from_numpy(synth.ricker(cs["nt"], cs["dt"], 15.0)[:, None].copy()).to("cuda")
-            opts = list(TIME_BLOCKING[8])
-        for o in opts:
-            for _ in range(args.warmup + args.steps):
-                _sweep(cs, o, nt=20)
-        torch.cuda.synchronize()
-        print(json.dumps({"profiled": args.kernel_only, "sweeps": args.warmup + args.steps, "steps": 20}),
-              flush=True)
-        return 0
-    cs = workload("cfg2")
-    npts = int(np.prod(cs["v"].shape))
-    tiled = launch_options("cfg2")
-    if args.headline_only_kernel:
-        for _ in range(args.warmup + args.steps):
-            _sweep(cs, tiled)
-        torch.cuda.synchronize()
-        print(json.dumps({"profiled": "cfg2 tiled", "sweeps": args.warmup + args.steps}), flush=True)
-        return 0
-    print(f"# cfg2 {cs['v'].shape} so{cs['so']} nt{cs['nt']}", file=sys.stderr, flush=True)
-    variants = {"untiled": dict(variant=1), "tiled": tiled, "time_tiled_T2": launch_options("cfg2_t2")}
-    res = {}
-    for k, o in variants.items():
-        ev, wall = time_block(lambda: _sweep(cs, o), args.steps, args.warmup)
-        med, mean, std = time_sweeps(cs, o, 3, 0)
-        res[k] = dict(ms=ev, wall_ms=wall, med_ms=med, std_ms=std, gpts=npts * cs["nt"] / (ev * 1e-3) / 1e9)
-    _sweep(cs, tiled)
-    cfg_used = api.last_config()
-
-    # roofline of the dominant kernel: the tiled sweep kernel of the headline
-    T = int(cfg_used["tblock"])
-    setup = setup_ms(cs, tiled)
-    launches = cs["nt"] // T + cs["nt"] % T
-    kern_ms = max(res["tiled"]["ms"] - setup, 1e-6) / launches
-    bytes_per_launch = (20 if T >= 2 else 16) * npts
-    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    traffic = profiled_traffic()
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"k_stream<M=4,T={T},PY={cfg_used['tile'][2]},NW={cfg_used['tile'][1] // cfg_used['tile'][2]}>",
-            "avg_launch_us": round(kern_ms * 1e3, 2), "launches": launches, "bytes_per_launch": bytes_per_launch,
-            "bytes_per_point": 20 if T >= 2 else 16}
-    ceil64 = streaming_ceiling(64)
-    roof["streaming_ceiling_tbs_64mib_fields"] = ceil64
-    roof["frac_of_streaming_ceiling"] = round(achieved / (ceil64 * 1000.0), 4)
+    # ---------------------------------------------------------------- headline: 512^3 so 16
+    print("# cfg3 512^3 so16 nt1000", file=sys.stderr, flush=True)
+    c3 = workload("cfg3")
+    n3 = int(np.prod(c3["v"].shape))
+    tiled = launch_options("cfg3")
+    ev, wall = time_block(lambda: _sweep(c3, tiled), args.steps, args.warmup)
+    med, mean, std = time_sweeps(c3, tiled, 3, 0)
+    _sweep(c3, tiled, nt=4)
+    cfg3_used = api.last_config()
+    setup3 = setup_ms(c3, tiled)
+    T = int(cfg3_used["tblock"])
+    launches = c3["nt"] // T + c3["nt"] % T
+    kname = kernel_name(cfg3_used, c3["so"])
+    roof = roofline_of(ev, setup3, launches, n3, 16 if T == 1 else 20, kname,
+                       profile="k_stream_512cube_so16_counters.txt")
+    roof["streaming_ceiling_tbs_512mib_fields"] = streaming_ceiling(512, reps=10)
+    roof["frac_of_streaming_ceiling"] = round(roof["achieved"] / (roof["streaming_ceiling_tbs_512mib_fields"] * 1000.0), 4)
+    gpts = n3 * c3["nt"] / (ev * 1e-3) / 1e9
+    variants = {"tiled": round(gpts, 2)}
+    for k, o in (("time_tiled_T2", T2), ("untiled", dict(variant=1))):
+        m, _, _ = time_sweeps(c3, o, 1, 1)
+        variants[k] = round(n3 * c3["nt"] / (m * 1e-3) / 1e9, 2)
     line = {
         "metric": METRIC,
-        "value": round(res["tiled"]["gpts"], 2),
+        "value": round(gpts, 2),
         "unit": "GPts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(res["tiled"]["ms"], 3),
+        "ms_per_step": round(ev, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "cfg2: 3-D 256^3, space order 8, 500 steps, smoothed random v (seed 1707, "
-                               "sigma 8 cells, 1.5-4.5 km/s), 15 Hz Ricker at depth 20, 20-cell sponge; one "
-                               "step = one whole 500-step sweep; tiled kernel from the autotuner's search "
-                               "space (time-block depth 1 wins on MI355X, T = 2 reported beside)",
-                   "launch": cfg_used, "parallelism": "single GPU"},
+        "config": {"workload": "cfg3: 3-D 512^3, space order 16, 1000 steps, smoothed random v (seed 1707, "
+                               "sigma 8 cells, 1.5-4.5 km/s), 15 Hz Ricker at depth 20, 40-cell sponge; one "
+                               "step = one whole 1000-step sweep; tiled kernel from the autotuner's cached "
+                               "choice (untiled and time-blocked T = 2 reported beside)",
+                   "launch": cfg3_used, "parallelism": "single GPU"},
         "roofline": roof,
-        "bw_equiv_frac_16B": round(res["tiled"]["gpts"] * 16 / HBM_PEAK_GBS, 4),
+        "bw_equiv_frac_16B": round(gpts * 16 / HBM_PEAK_GBS, 4),
         # the same at the 20 B per point a Devito-style count gives (it also
         # streams m and damp; this build derives damp from 1-D profiles)
-        "bw_equiv_frac_20B": round(res["tiled"]["gpts"] * 20 / HBM_PEAK_GBS, 4),
-        "variants_gpts": {k: round(v["gpts"], 2) for k, v in res.items()},
-        "wall_ms_per_step": round(res["tiled"]["wall_ms"], 3),
-        "variants_ms_block_median_std": {k: [round(v["ms"], 3), round(v["med_ms"], 3), round(v["std_ms"], 3)]
-                                         for k, v in res.items()},
+        "bw_equiv_frac_20B": round(gpts * 20 / HBM_PEAK_GBS, 4),
+        "variants_gpts": variants,
+        "wall_ms_per_step": round(wall, 3),
+        "ms_block_median_std": [round(ev, 3), round(med, 3), round(std, 3)],
     }
+    # ---------------------------------------------------------------- the tiled adjoint sweep
+    print("# adjoint sweeps", file=sys.stderr, flush=True)
+    adj = {}
+    rec3, res3 = adjoint_case(c3)
+    am, _, _ = _timed(lambda: _adjoint(c3, rec3, res3, tiled), 2, 1)
+    _adjoint(c3, rec3, res3, tiled, nt=4)
+    acfg = api.last_config()
+    asetup = _timed(lambda: _adjoint(c3, rec3, res3, tiled, nt=0), 3, 1)[0]
+    ar = roofline_of(am, asetup, c3["nt"] // int(acfg["tblock"]) + c3["nt"] % int(acfg["tblock"]), n3, 16,
+                     kernel_name(acfg, c3["so"]), profile="k_stream_512cube_so16_adjoint_counters.txt")
+    adj["cfg3"] = {"gpts": round(n3 * c3["nt"] / (am * 1e-3) / 1e9, 2), "ms": round(am, 2), "launch": acfg,
+                   "roofline": ar, "config": "cfg3 grid; residual traces injected at 256 receivers (depth 20), "
+                                             "result recorded at the source"}
+    del rec3, res3, c3
+    torch.cuda.empty_cache()
+    # ---------------------------------------------------------------- 256^3 so 8 (cache-resident)
+    print("# cfg2 256^3 so8 nt500 (cache-resident)", file=sys.stderr, flush=True)
+    cs = workload("cfg2")
+    npts = int(np.prod(cs["v"].shape))
+    c2 = {}
+    for k, o in (("tiled", launch_options("cfg2")), ("untiled", dict(variant=1)), ("time_tiled_T2", T2)):
+        e2, _ = time_block(lambda: _sweep(cs, o), max(3, args.steps // 2), 1)
+        c2[k] = round(npts * cs["nt"] / (e2 * 1e-3) / 1e9, 2)
+        if k == "tiled":
+            ev2 = e2
+    _sweep(cs, launch_options("cfg2"), nt=4)
+    cfg2_used = api.last_config()
+    r2 = roofline_of(ev2, setup_ms(cs, launch_options("cfg2")), cs["nt"] // int(cfg2_used["tblock"]) +
+                     cs["nt"] % int(cfg2_used["tblock"]), npts, 16, kernel_name(cfg2_used, cs["so"]),
+                     profile="k_stream_cfg2_counters.txt")
+    r2["streaming_ceiling_tbs_64mib_fields"] = streaming_ceiling(64)
+    line["cfg2_cache_resident"] = {
+        "gpts": c2, "launch": cfg2_used, "roofline": r2,
+        "note": "256^3 so 8, 500 steps: three 64 MiB fields stay in the 256 MB Infinity Cache between steps, "
+                "so this rate is not bound by HBM"}
+    rec2, res2 = adjoint_case(cs)
+    am2, _, _ = _timed(lambda: _adjoint(cs, rec2, res2, launch_options("cfg2")), 3, 1)
+    adj["cfg2_cache_resident"] = {"gpts": round(npts * cs["nt"] / (am2 * 1e-3) / 1e9, 2), "ms": round(am2, 2)}
+    del rec2, res2
+    line["adjoint"] = adj
     if not args.quick:
-        print("# cfg3", file=sys.stderr, flush=True)
-        c3 = workload("cfg3")
-        n3 = int(np.prod(c3["v"].shape))
-        r3 = {}
-        for k, o in {"tiled": launch_options("cfg3"), "time_tiled_T2": launch_options("cfg3_t2"),
-                     "untiled": dict(variant=1)}.items():
-            med, _, _ = time_sweeps(c3, o, 1, 1)
-            r3[k] = round(n3 * c3["nt"] / (med * 1e-3) / 1e9, 2)
-        line["cfg3_512cube_so16_gpts"] = r3
-        line["cfg3_bw_equiv_frac_16B"] = round(r3["tiled"] * 16 / HBM_PEAK_GBS, 4)
-        line["cfg3_streaming_ceiling_tbs_512mib_fields"] = streaming_ceiling(512, reps=10)
-        del c3
-        torch.cuda.empty_cache()
         print("# time blocking at 512^3", file=sys.stderr, flush=True)
         line["time_blocking_512cube_gpts"] = time_blocking_study()
         print("# cfg4", file=sys.stderr, flush=True)
@@ -592,10 +657,65 @@ def main():
         except Exception as e:  # report, do not lose the line
             line["cfg5_batched"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
+    del cs
+    torch.cuda.empty_cache()
     if not args.no_oracle:
         print("# oracle baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = oracle_baseline(cs)
+        line["cpu_baseline"] = oracle_baseline(workload("cfg3"), budget_s=15.0)
     print(json.dumps(line), flush=True)
+    return 0
+
+
+def kernel_only(args):
+    """Short runs of one workload for profiling (kernel trace or counters)."""
+    import torch
+
+    import synth
+    from paper_1707_02347_amd import api
+
+    n = args.warmup + args.steps
+    what = args.kernel_only
+    if what == "batch":
+        shots = batch_shots()
+        for _ in range(n):
+            api.forward_batch(shots, graph=True)
+    elif what == "sinc":
+        cs = offgrid(dict(workload("cfg2"), rec=synth.receiver_line((256,) * 3, 256, depth=20)))
+        cs = dict(cs, src=api.Sinc(cs["src"], 4), rec=api.Sinc(cs["rec"], 4))
+        for _ in range(n):
+            _sweep(cs, launch_options("cfg2"), nt=20)
+    elif what == "born":
+        cs = workload("cfg2")
+        rec = synth.receiver_line(cs["v"].shape, 256, depth=20)
+        dv = 0.05 * (synth.blob_velocity(cs["v"], amp=1.0, width_frac=1.0 / 16.0) - cs["v"])
+        for _ in range(n):
+            api.born(cs["v"], cs["h"], cs["so"], 20, cs["dt"], cs["src"], cs["amp"][:20].contiguous(), rec, dv,
+                     sponge=cs["sponge"], vref=cs["vref"], **launch_options("cfg2"))
+    elif what == "cfg2":
+        cs = workload("cfg2")
+        for _ in range(n):
+            _sweep(cs, launch_options("cfg2"))
+    elif what == "cfg3-adjoint":
+        cs = workload("cfg3")
+        rec, res = adjoint_case(cs)
+        for _ in range(n):
+            _adjoint(cs, rec, res, launch_options("cfg3"))
+    else:
+        cs = workload("cfg3")
+        opts = [launch_options("cfg3")]
+        if what == "tblock-so8":
+            cs["so"] = 8
+            cs["dt"] = 0.8 * courant_max(8, 3) * 10.0 / 4500.0
+            cs["amp"] = torch.from_numpy(synth.ricker(cs["nt"], cs["dt"], 15.0)[:, None].copy()).to("cuda")
+            opts = list(TIME_BLOCKING[8])
+        # whole sweeps for the headline kernel (a launch's time varies along the
+        # sweep, so only the whole sweep's average compares with the benchmark)
+        steps = cs["nt"] if what == "cfg3" else 20
+        for o in opts:
+            for _ in range(n):
+                _sweep(cs, o, nt=steps)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": what, "runs": n, "launch": api.last_config()}), flush=True)
     return 0
 
 

@@ -366,6 +366,22 @@ int fd_forward_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_byte
 int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes,
                       uint32_t batch_flags, void *stream);
 
+/*
+ * Autotuner of a batch, the grouped launches' counterpart of fd_autotune (the
+ * auto-tuned blocking of the paper's control runs, Sec. 6.6.1): for each class
+ * of shots of one space order whose options are automatic (variant 0), times
+ * a few steps of the class's grouped forward launches under every grouped
+ * kernel shape compiled for it (tile rows, rows per thread, time-block depth
+ * 1..4) and two chunk lengths, and writes the fastest into the options of
+ * every shot of the class (one shared kernel keeps the class's passes in one
+ * grouped launch per round; the shots' flags and ckpt_every are kept).  Shots
+ * with explicit options are left as they are.  The timing runs sweep the shots
+ * with their sources only (no receiver or gradient buffer is written).
+ * workspace: at least fd_batch_workspace_size(nshots, shots, FD_OP_FORWARD)
+ * bytes (a gradient batch's workspace is larger).  Synchronises the stream.
+ */
+int fd_batch_autotune(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes, void *stream);
+
 /* Static text for a status code. */
 const char *fd_strerror(int code);
 

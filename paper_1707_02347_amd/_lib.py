@@ -139,6 +139,7 @@ SYMBOLS = {
                                    C.c_void_p]),
     "fd_gradient_batch": (C.c_int, [C.c_int, C.POINTER(fd_shot), C.c_void_p, C.c_size_t, C.c_uint32,
                                     C.c_void_p]),
+    "fd_batch_autotune": (C.c_int, [C.c_int, C.POINTER(fd_shot), C.c_void_p, C.c_size_t, C.c_void_p]),
     "fd_strerror": (C.c_char_p, [C.c_int]),
     "fd_version": (C.c_int, []),
     "fd_last_config": (C.c_int, [C.POINTER(fd_options)]),
@@ -218,6 +219,10 @@ def fd_forward_batch(nshots, shots, workspace, ws_bytes, flags, stream):
 
 def fd_gradient_batch(nshots, shots, workspace, ws_bytes, flags, stream):
     return load().fd_gradient_batch(nshots, shots, workspace, ws_bytes, flags, stream)
+
+
+def fd_batch_autotune(nshots, shots, workspace, ws_bytes, stream):
+    return load().fd_batch_autotune(nshots, shots, workspace, ws_bytes, stream)
 
 
 def fd_version():

@@ -251,3 +251,25 @@ def gradient_batch(shots, graph=True):
                              L._stream(dev))
     L._check(rc, "fd_gradient_batch")
     return [float(arr[i].misfit) for i in range(len(shots))], [o["grad_v"] for o in outs]
+
+
+def batch_autotune(shots):
+    """Let the library's batch tuner choose one kernel per space-order class for
+    the shots whose options are automatic; updates each shot's ``options`` dict
+    (variant, tile, tblock) in place and returns the list of chosen options."""
+    keep = []
+    arr = (L.fd_shot * len(shots))()
+    for i, sh in enumerate(shots):
+        arr[i], _ = _shot_struct(sh, L.FD_OP_FORWARD, keep)
+    nbytes = L.fd_batch_workspace_size(len(shots), arr, L.FD_OP_FORWARD)
+    dev = shots[0]["v"].device
+    ws = _workspace(nbytes, dev)
+    rc = L.fd_batch_autotune(len(shots), arr, L._ptr(ws), ws.numel(), L._stream(dev))
+    L._check(rc, "fd_batch_autotune")
+    out = []
+    for i, sh in enumerate(shots):
+        o = arr[i].opts
+        chosen = {"variant": int(o.variant), "tile": tuple(int(t) for t in o.tile), "tblock": int(o.tblock)}
+        sh["options"] = dict(sh.get("options", {}), **chosen)
+        out.append(chosen)
+    return out

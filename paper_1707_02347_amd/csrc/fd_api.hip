@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -589,6 +590,18 @@ KernelKey key_for(const KernelKey &base, int T, int mode, bool iso)
     return KernelKey{base.M, 1, 8, 4, mode};
 }
 
+// A compiled shape of the same radius, depth and mode whose kernel can stage
+// point entries in LDS, in order of preference; M = 0 if there is none.
+KernelKey stageable_key(const KernelKey &k, bool iso)
+{
+    static const int shapes[][2] = {{4, 8}, {4, 4}, {8, 4}, {2, 8}};
+    for (auto &sh : shapes) {
+        const KernelKey c{k.M, k.T, sh[0], sh[1], k.mode};
+        if (points_stageable(c.M, c.T, c.PY, c.NW) && stream_has(c, iso)) return c;
+    }
+    return KernelKey{0, 0, 0, 0, 0};
+}
+
 // ------------------------------------------------------------------ point tables
 struct Entry {
     int x, y, z, id;
@@ -1155,6 +1168,15 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
             const int kmode = isep ? (int)kPlain : so.mode;
             k = (T == c.plan.key.T && kmode == kPlain) ? c.plan.key : key_for(c.plan.key, T, kmode, iso);
             if (k.T != T) k = key_for(c.plan.key, 1, kmode, iso);
+            // a shape that cannot stage point entries (a tuned choice, made
+            // without points, can be one) would walk a pass's tables of more
+            // than a few entries in memory, serially: take a stageable shape
+            // of the same depth and mode for such passes
+            if (!points_stageable(k.M, k.T, k.PY, k.NW) &&
+                ((!isep && a0.inj.cnt > kStageMin) || (!rsep && a0.rec.cnt > kStageMin))) {
+                const KernelKey sk = stageable_key(k, iso);
+                if (sk.M) k = sk;
+            }
             a.u0 = st.cur;
             a.um = st.prev;
             o2 = nullptr;
@@ -2421,6 +2443,108 @@ extern "C" int fd_gradient_batch(int nshots, fd_shot *shots, void *workspace, si
                                   (batch_flags & FD_BATCH_GRAPH) != 0, (hipStream_t)stream);
         if (rc) return rc;
         for (int i = 0; i < nshots; ++i) shots[i].misfit = grad_misfit(jobs[i]);
+        return FD_OK;
+    });
+}
+
+// ====================================================================== batch autotuner
+namespace fdw {
+namespace {
+
+// Kernel shapes a class of batched shots can share: compiled as grouped
+// kernels for the Laplacian form of every shot in the class.
+std::vector<KernelKey> batch_candidates(int M, const std::vector<bool> &forms)
+{
+    static const int shapes[][2] = {{4, 8}, {4, 4}, {8, 4}, {2, 16}, {2, 8}, {8, 2}, {16, 2}};
+    std::vector<KernelKey> out;
+    for (int T = 1; T <= 4; ++T)
+        for (auto &sh : shapes) {
+            const KernelKey k{M, T, sh[0], sh[1], kPlain};
+            bool ok = true;
+            for (bool iso : forms) ok = ok && stream_has_group(k, iso);
+            if (ok) out.push_back(k);
+        }
+    return out;
+}
+
+}  // namespace
+}  // namespace fdw
+
+extern "C" int fd_batch_autotune(int nshots, fd_shot *shots, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&]() -> int {
+        if (nshots < 0 || (nshots > 0 && !shots)) return FD_EINVAL;
+        if (!workspace || ((uintptr_t)workspace & 255)) return FD_EWORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        // classes: shots of one stencil radius whose options are automatic
+        std::map<int, std::vector<int>> cls;
+        for (int i = 0; i < nshots; ++i) {
+            Dims d;
+            if (make_dims(&shots[i].grid, d)) return FD_EINVAL;
+            if (shots[i].opts.variant == FD_VARIANT_AUTO) cls[d.M].push_back(i);
+        }
+        // seconds per step of a class under options o: two forward runs of n1
+        // and n2 = 3 n1 steps (sources only: no receiver buffer is written),
+        // differenced, which removes each call's set-up
+        constexpr int n1 = 12, n2 = 36;  // multiples of every depth 1..4
+        auto run = [&](const std::vector<int> &idx, const fd_options &o, int nt) -> double {
+            std::vector<fd_shot> sub;
+            for (int i : idx) {
+                fd_shot x = shots[i];
+                x.time.nt = std::min<int64_t>(x.time.nt, nt);
+                x.rec = fd_points{};
+                x.rec_out = nullptr;
+                x.grad_v = nullptr;
+                const uint32_t keep = x.opts.flags;
+                x.opts = o;
+                x.opts.flags = keep;
+                sub.push_back(x);
+            }
+            const size_t need = fd_batch_workspace_size((int)sub.size(), sub.data(), FD_OP_FORWARD);
+            if (!need || need > ws_bytes) throw Status{FD_EWORKSPACE};
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = fd_forward_batch((int)sub.size(), sub.data(), workspace, ws_bytes, 0, stream);
+            if (rc) throw Status{rc};
+            FDW_HIP(hipStreamSynchronize(s));
+            return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        };
+        for (auto &kv : cls) {
+            const std::vector<int> &idx = kv.second;
+            std::vector<bool> forms;
+            for (int i : idx) {
+                Dims d;
+                make_dims(&shots[i].grid, d);
+                forms.push_back(grid_iso(d));
+            }
+            double best = 1e300;
+            fd_options best_o{};
+            bool found = false;
+            for (const KernelKey &k : batch_candidates(kv.first, forms)) {
+                for (int lx : {0, 128}) {  // automatic chunk (at least 64 planes), or 128
+                    fd_options o{};
+                    o.variant = k.T == 1 ? FD_VARIANT_STREAM : FD_VARIANT_TBLOCK;
+                    o.tile[0] = lx;
+                    o.tile[1] = k.PY * k.NW;
+                    o.tile[2] = k.PY;
+                    o.tblock = k.T;
+                    (void)run(idx, o, n1);  // warm-up
+                    const double t = run(idx, o, n2) - run(idx, o, n1);
+                    if (t < best) {
+                        best = t;
+                        best_o = o;
+                        found = true;
+                    }
+                }
+            }
+            if (!found) continue;  // no grouped kernel for this class: automatic plans stay
+            for (int i : idx) {
+                const uint32_t keep = shots[i].opts.flags;
+                const int32_t ck = shots[i].opts.ckpt_every;
+                shots[i].opts = best_o;
+                shots[i].opts.flags = keep;
+                shots[i].opts.ckpt_every = ck;
+            }
+        }
         return FD_OK;
     });
 }

@@ -373,6 +373,36 @@ int main()
         for (auto &s : gmix) s.o.ckpt_every = 11;
         batch_case(bf ? "graph" : "direct", gmix, true, bf, 0);
     }
+    // the batch tuner on the mixed batch (automatic shots tuned per class)
+    {
+        std::vector<fd_shot> shots(mix.size());
+        std::vector<Pts> srcs;
+        std::vector<Buf *> bufs;
+        srcs.reserve(mix.size());
+        for (size_t i = 0; i < mix.size(); ++i) {
+            fd_shot &sh = shots[i];
+            std::memset(&sh, 0, sizeof sh);
+            sh.grid = grid(mix[i].n, mix[i].so);
+            sh.time = fd_time{mix[i].nt, stable_dt(sh.grid)};
+            Buf *v = new Buf(points(sh.grid) * 4);
+            for (int64_t k = 0; k < points(sh.grid); ++k) v->f()[k] = 2000.0f;
+            Buf *amp = new Buf((size_t)mix[i].nt * 4);
+            bufs.push_back(v);
+            bufs.push_back(amp);
+            sh.v = v->f();
+            srcs.push_back(centre_src(sh.grid, mix[i].n.back() / 3));
+            srcs.back().p.amp = amp->f();
+            sh.src = srcs.back().p;
+            sh.opts = mix[i].o;
+        }
+        const size_t ws = fd_batch_workspace_size((int)shots.size(), shots.data(), FD_OP_FORWARD);
+        Buf w(ws);
+        expect(fd_batch_autotune((int)shots.size(), shots.data(), w.p, ws, nullptr), FD_OK, "batch autotune");
+        for (size_t i = 0; i < shots.size(); ++i)
+            if (mix[i].o.variant == 0 && (shots[i].opts.variant < FD_VARIANT_STREAM || shots[i].opts.tile[2] <= 0))
+                expect(-100, FD_OK, "batch autotune sets the options of automatic shots");
+        for (Buf *b : bufs) delete b;
+    }
     const std::vector<ShotSpec> three = {
         {{40, 38, 44}, 4, 24, opts()}, {{36, 44, 52}, 8, 21, opts()}, {{48, 40, 46}, 16, 18, opts()}};
     for (uint32_t f : {0u, (uint32_t)FD_FLAG_LOADS_STREAM, (uint32_t)FD_FLAG_LOADS_KEEP})

@@ -93,3 +93,24 @@ def test_full_size_batch_shots_equal_single_shots():
                           sponge=s["sponge"], vref=s["vref"], **o)["rec"]
         assert torch.equal(tr, ref), (s["v"].shape, s["so"])
         assert float(ref.abs().max()) > 0
+
+
+def test_batch_autotune_shares_one_kernel_per_order_and_keeps_the_bits():
+    """The batch tuner gives every automatic shot of one space order the same
+    compiled configuration, leaves explicit options alone, and the tuned batch
+    returns the same traces bit for bit."""
+    shots = make_shots()
+    explicit = [dict(sh["options"]) for sh in shots]
+    ref = [t.clone() for t in api.forward_batch(shots, graph=True)]
+    chosen = api.batch_autotune(shots)
+    by_order = {}
+    for sh, ex, ch in zip(shots, explicit, chosen):
+        if ex:  # explicit options are kept
+            assert ch["variant"] == ex["variant"] and ch["tblock"] == ex["tblock"]
+            continue
+        assert ch["variant"] in (L.FD_VARIANT_STREAM, L.FD_VARIANT_TBLOCK) and ch["tblock"] >= 1
+        by_order.setdefault(sh["so"], set()).add((ch["variant"], ch["tile"], ch["tblock"]))
+    assert by_order and all(len(v) == 1 for v in by_order.values()), by_order
+    outs = api.forward_batch(shots, graph=True)
+    for a, b in zip(outs, ref):
+        assert torch.equal(a, b)
