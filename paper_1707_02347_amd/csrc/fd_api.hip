@@ -1086,8 +1086,9 @@ struct StepOpts {
 // Super-tile of the XCD-aware tile order (see SweepArgs::remap): gx x-chunks by
 // gy y-tiles by all z-tiles, with a multiple of 8 super-tiles.  Among the
 // admissible shapes, pick the one whose faces to other XCDs re-read the least
-// of u per tile: a y face costs M rows of the (RZ + 2M)-wide halo ring against
-// RY x RZ owned points, an x face costs T M warm-up planes against lx planes.
+// of u per tile: a y face costs M rows of (RZ + 2M) columns (the halo band
+// and the lines its ends touch) against RY x RZ owned points, an x face costs
+// T M warm-up planes against lx planes.
 // Without an admissible shape the hardware order is kept.
 void supertile(const KernelKey &k, SweepArgs &a)
 {

@@ -48,7 +48,10 @@ struct Geo {
     static constexpr int L0H = RY + 2 * M;       // level-0 LDS plane (owned region + halo M)
     static constexpr int L0W = RZ + 2 * M;
     static constexpr int Q = 2 * M + 1;          // register queue length along x
-    static constexpr int NHALO = 2 * M * L0W + RY * 2 * M;
+    // the M-wide ring of the level-0 plane without its corners (the star
+    // stencil never reads them): M rows above and below the owned columns, M
+    // columns left and right of the owned rows
+    static constexpr int NHALO = 2 * M * RZ + RY * 2 * M;
     static constexpr int HS = (NHALO + NT - 1) / NT;
     static constexpr int AQ = (T - 1) * M + 1;   // imaging accumulator queue length
     static constexpr int SPAN = kMaxLx + 2 * (T - 1) * M + 2;  // per-plane table entries
@@ -502,12 +505,12 @@ struct StreamKernel {
     // Position (row, col) in the level-0 LDS plane of halo slot h; false if unused.
     __device__ static __forceinline__ bool halo_pos(int h, int &row, int &col)
     {
-        if (h < 2 * M * G::L0W) {
-            const int band = h / G::L0W;
-            col = h - band * G::L0W;
+        if (h < 2 * M * G::RZ) {
+            const int band = h / G::RZ;
+            col = M + (h - band * G::RZ);
             row = band < M ? band : band + G::RY;
         } else {
-            const int h2 = h - 2 * M * G::L0W;
+            const int h2 = h - 2 * M * G::RZ;
             row = M + h2 / (2 * M);
             const int cj = h2 % (2 * M);
             col = cj < M ? cj : cj + G::RZ;
