@@ -103,6 +103,16 @@ extern "C" {
 #define FD_VARIANT_STREAM 2  /* space-tiled: (y,z) tile per workgroup, x streamed
                                 through a register queue, y/z neighbours via LDS */
 #define FD_VARIANT_TBLOCK 3  /* time-blocked streaming: T levels per HBM pass */
+#define FD_VARIANT_SPLIT 4   /* time-blocked, two levels per pass, with split tiles along
+                                the streamed axis x (Pochoir-style trapezoids, paper
+                                Sec. 2.5): chunks tile x without overlap, each computes
+                                an upright trapezoid (level 1 on its planes, level 2 on
+                                them less M at each shared end), and a second, single-
+                                level phase fills the inverted trapezoids (level 2 on the
+                                2M planes around each shared end); no plane of level 1 is
+                                computed twice.  Passes with more than 32 receiver
+                                entries use TBLOCK's overlapped chunks.  tblock must
+                                be 0 or 2. */
 
 /* ------------------------------------------------------------------ flags */
 #define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */

@@ -32,6 +32,7 @@ FD_VARIANT_AUTO = 0
 FD_VARIANT_NAIVE = 1
 FD_VARIANT_STREAM = 2
 FD_VARIANT_TBLOCK = 3
+FD_VARIANT_SPLIT = 4
 
 FD_FLAG_NO_CFL_CHECK = 1
 FD_FLAG_CHECK_FINITE = 2

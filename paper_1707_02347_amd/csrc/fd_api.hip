@@ -389,12 +389,13 @@ int fields_needed(int op)
 
 // ------------------------------------------------------------------ planning
 struct Plan {
-    int variant;      // FD_VARIANT_NAIVE / STREAM / TBLOCK
+    int variant;      // FD_VARIANT_NAIVE / STREAM / TBLOCK / SPLIT
     KernelKey key;    // for stream / tblock (mode set per use)
     int lx;
     bool remap;
     bool alt;
     int loads;        // cache policy of once-per-step loads: -1 automatic, 0 keep, 1 stream
+    bool split = false;  // two-level plain passes split into trapezoids along x
 };
 
 std::mutex g_tune_mu;
@@ -549,9 +550,14 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         p.lx = d.nx;
         return FD_OK;
     }
-    if (eff.variant != FD_VARIANT_STREAM && eff.variant != FD_VARIANT_TBLOCK) return FD_EINVAL;
+    if (eff.variant != FD_VARIANT_STREAM && eff.variant != FD_VARIANT_TBLOCK && eff.variant != FD_VARIANT_SPLIT)
+        return FD_EINVAL;
     int T = 1;
     if (eff.variant == FD_VARIANT_TBLOCK) T = eff.tblock > 0 ? eff.tblock : 2;
+    if (eff.variant == FD_VARIANT_SPLIT) {
+        if (eff.tblock != 0 && eff.tblock != 2) return FD_EINVAL;
+        T = 2;
+    }
     if (T < 1 || T > 4) return FD_EINVAL;
     KernelKey k;
     if (eff.tile[1] > 0 || eff.tile[2] > 0) {
@@ -569,6 +575,13 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
     p.key = k;
     p.variant = (k.T >= 2) ? FD_VARIANT_TBLOCK : FD_VARIANT_STREAM;
     p.lx = eff.tile[0] > 0 ? std::min(std::min(eff.tile[0], d.nx), kMaxLx) : default_lx(d, k);
+    if (eff.variant == FD_VARIANT_SPLIT) {
+        if (k.T != 2) return FD_EUNSUPPORTED;
+        // an upright trapezoid needs level 2 on at least one plane of its chunk
+        p.lx = std::max(p.lx, std::min(d.nx, 2 * k.M + 1));
+        p.variant = FD_VARIANT_SPLIT;
+        p.split = true;
+    }
     return FD_OK;
 }
 
@@ -903,6 +916,7 @@ struct Ctx {
     SweepArgs base;   // common launch arguments
     std::vector<int32_t> hxs, hxr;  // host copies of the point tables' plane pointers
     int ran_T = 0;    // deepest time block a pass of this call used (0: none yet)
+    bool ran_split = false;  // a pass of this call ran split along x
 };
 
 // Whether a pass walks its point entries staged in LDS: a configuration that
@@ -1220,7 +1234,42 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         if (isep) a.inj = PointTable{};
         a.ps = stage_points(c, k, a) ? 1 : 0;
         supertile(k, a);
+        // split trapezoids along x: plain two-level passes that span more than
+        // one chunk, with at most a few receivers (their entries are walked in
+        // memory: the staged walk records each entry for every level of its
+        // own chunk, which a split chunk does not compute; larger tables keep
+        // the overlapped chunks)
+        const bool split = c.plan.split && k.T == 2 && k.mode == kPlain && a.rec.cnt <= kStageMin && a.ntx >= 2;
+        a.split = split ? 1 : 0;
+        if (split && a.rec.cnt > 0) a.ps = 0;
         c.ex.pass(k, a, c.plan.loads);
+        c.ran_split = c.ran_split || split;
+        if (split) {
+            // the inverted trapezoids: level 2 on the 2M planes around each
+            // shared chunk end, from the level-1 field the first phase stored
+            // in full (o2) and u^n (the pass's u0)
+            const KernelKey k1 = key_for(k, 1, kPlain, iso);
+            SweepArgs b = a;
+            b.split = 0;
+            b.u0 = o2;
+            b.um = a.u0;
+            b.o1 = o1;
+            b.o2 = nullptr;
+            b.step0 = a.step0 + 1;
+            b.lx = 2 * d.M;
+            b.xoff = a.lx - d.M;
+            b.xstride = a.lx;
+            b.ntx = a.ntx - 1;
+            const int ty = stream_core_rows(k1), tz = stream_core_cols(k1);
+            b.ntz = (d.nz + tz - 1) / tz;
+            b.nty = (d.ny + ty - 1) / ty;
+            b.remap = 0;
+            b.alt = 0;
+            b.gx = b.gy = 1;
+            b.ps = 0;  // a few planes per chunk: the entries are walked in memory
+            b.ntl = stream_loads(c.plan.loads, resident_bytes(b, kPlain), 1) ? 1 : 0;
+            c.ex.pass(k1, b, c.plan.loads);
+        }
         if (rsep) {
             const int mode = so.mode;
             const float *cur = st.cur, *prev = st.prev;
@@ -1303,7 +1352,10 @@ void record_last(const Ctx &c)
     g_last.tile[1] = p.key.NW * p.key.PY;
     g_last.tile[2] = p.key.PY;
     g_last.tblock = c.ran_T > 0 ? c.ran_T : p.key.T;
-    if (p.variant == FD_VARIANT_TBLOCK && c.ran_T == 1) g_last.variant = FD_VARIANT_STREAM;
+    if ((p.variant == FD_VARIANT_TBLOCK || p.variant == FD_VARIANT_SPLIT) && c.ran_T == 1)
+        g_last.variant = FD_VARIANT_STREAM;
+    else if (p.variant == FD_VARIANT_SPLIT && !c.ran_split)
+        g_last.variant = FD_VARIANT_TBLOCK;
     g_last_valid = true;
 }
 
@@ -1984,20 +2036,22 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
     };
     if (fixed.variant == 0 || fixed.variant == FD_VARIANT_NAIVE) push(FD_VARIANT_NAIVE, 0, 0, 0, 1);
     static const int shapes[][2] = {{4, 8}, {4, 4}, {2, 16}, {8, 4}, {16, 2}, {8, 2}};
-    for (int T = 1; T <= 4; ++T) {
-        const int variant = T == 1 ? FD_VARIANT_STREAM : FD_VARIANT_TBLOCK;
+    for (int T = 1; T <= 5; ++T) {
+        // T = 5 stands for the split form of two-level passes
+        const int variant = T == 1 ? FD_VARIANT_STREAM : T == 5 ? FD_VARIANT_SPLIT : FD_VARIANT_TBLOCK;
+        const int depth = T == 5 ? 2 : T;
         if (fixed.variant && fixed.variant != variant) continue;
-        if (fixed.tblock && fixed.tblock != T) continue;
+        if (fixed.tblock && fixed.tblock != depth) continue;
         for (auto &sh : shapes) {
-            KernelKey k{d.M, T, sh[0], sh[1], kPlain};
+            KernelKey k{d.M, depth, sh[0], sh[1], kPlain};
             if (!stream_has(k, grid_iso(d))) continue;
             const int lx0 = default_lx(d, k);
             int last = -1;
             for (int f : {1, 2, 4, 8}) {  // lx0 / 2, lx0, 2 lx0, 4 lx0
-                const int lx = std::min(std::min(d.nx, kMaxLx), std::max(4 * T * d.M, lx0 * f / 2));
+                const int lx = std::min(std::min(d.nx, kMaxLx), std::max(4 * depth * d.M, lx0 * f / 2));
                 if (lx == last) continue;
                 last = lx;
-                push(variant, lx, sh[0] * sh[1], sh[0], T);
+                push(variant, lx, sh[0] * sh[1], sh[0], depth);
             }
         }
     }
@@ -2277,8 +2331,12 @@ int run_merged(std::vector<std::vector<Op>> &ops, const std::vector<int> &shot_l
             // one workgroup per tile: the hardware dispatcher balances the uneven
             // tiles of different shots (measured on MI355X, 7 % faster for the
             // 32-shot batch than a persistent grid of one workgroup per
-            // resident slot walking the table; the kernel supports both)
-            L.grid = L.total;
+            // resident slot walking the table; the kernel supports both).  The
+            // grid is padded to a multiple of 8, the XCD count, so that the
+            // kernel deals each XCD a contiguous block of tiles (neighbouring
+            // tiles of a shot then share that XCD's L2); the padding workgroups
+            // find no tile and exit.
+            L.grid = (L.total + 7) / 8 * 8;
             // the shots of one grouped launch stream side by side: their fields
             // compete for the cache together
             L.ntl = stream_loads(lead.loads, resident, lead.key.T);

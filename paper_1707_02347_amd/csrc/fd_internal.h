@@ -98,6 +98,16 @@ struct SweepArgs {
     // ps != 0: the point entries of every chunk fit in LDS and are staged there
     // (single-pass launches; a grouped launch takes the choice as an argument).
     int ps;
+    // Chunk placement along x: chunk bx starts at plane xoff + bx * xstride
+    // (xstride 0: lx) and spans lx planes.
+    int xoff, xstride;
+    // split != 0 (two-level plain passes): the first phase of a pass split into
+    // upright and inverted trapezoids along x.  Chunks tile x without overlap:
+    // level 1 is computed on the chunk's own planes and stored there in full,
+    // level 2 on them less M planes at each end another chunk shares; the
+    // second phase, a single-level pass over the 2M planes around each shared
+    // end, fills level 2 in those gaps.
+    int split;
 };
 
 // Point entries x time levels a workgroup can stage in LDS, the configurations

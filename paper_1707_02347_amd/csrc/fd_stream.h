@@ -250,8 +250,16 @@ struct StreamKernel {
         const int y1 = by * G::TY - G::H1;
 
         Thread th;
-        th.x0 = bx * a.lx;
+        th.x0 = a.xoff + bx * (a.xstride > 0 ? a.xstride : a.lx);
         th.xend = min(th.x0 + a.lx, a.nx);
+        if constexpr (T == 2 && MODE == kPlain) {
+            // first phase of a split pass: the chunk's planes are its base (level
+            // 1); level 2 leaves out M planes at each end another chunk shares
+            if (a.split) {
+                if (th.x0 > 0) th.x0 += M;
+                if (th.xend < a.nx) th.xend -= M;
+            }
+        }
         // stream position i maps to plane i (upward) or x0 + xend - 1 - i
         // (downward); the set of planes a chunk touches is symmetric under
         // that reflection, so both directions visit the same planes, and the
@@ -794,7 +802,12 @@ struct StreamKernel {
                 if constexpr (FUSED) recv[r] = out2[r];
                 else recv[r] = out[r];
             }
-            if (c >= th.x0 && c < th.xend) {
+            // receivers record the levels a workgroup owns: its chunk's planes,
+            // and in the first phase of a split pass every plane level 1
+            // computes (the walk in memory only: such passes do not stage)
+            bool rown = c >= th.x0 && c < th.xend;
+            if constexpr (T == 2 && t == 1 && MODE == kPlain) rown = rown || a.split != 0;
+            if (rown) {
                 const int jb = __builtin_amdgcn_readfirstlane(sm.rxb[tj]);
                 const int je = __builtin_amdgcn_readfirstlane(sm.rxe[tj]);
                 if (jb < je) {
@@ -842,6 +855,15 @@ struct StreamKernel {
 #pragma unroll
                 for (int r = 0; r < PY; ++r) out2[r] = 0.0f;
             }
+        }
+        if constexpr (T == 2 && t == 1 && MODE == kPlain) {
+            // first phase of a split pass: level 1 is stored on the chunk's
+            // planes outside level 2's range too (the second phase reads it);
+            // an empty resource otherwise, so the store is issued unconditionally
+            const bool wing = a.split != 0 && xin && (c < th.x0 || c >= th.xend) && needed(a, th, 1, c);
+            const auto rw = plane_rsrc(a.o2, c, a.sxy, wing);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) bstore<kStream>(rw, out_off(th, r), out[r]);
         }
         // gradient support (outside the branch above, so that every memory
         // operation of the iteration is issued unconditionally; own planes are

@@ -5,6 +5,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Automatic plans take the autotuner's cached choices, as in bench.py, so that
+# the full-size tests run the configurations the benchmark times.
+os.environ.setdefault("FD_AUTOTUNE_CACHE", os.path.join(ROOT, "paper_1707_02347_amd", "autotune_gfx950.txt"))
+
 # GPU test files in the order they run: comparisons with the FP64 oracle
 # first, so that a failure in a later file (which stops a run under -x)
 # cannot hide them; batches, whose launches share the most host state,
@@ -12,6 +16,7 @@ if ROOT not in sys.path:
 # Files not listed keep their place among themselves after the listed ones.
 ORDER = [
     "test_gpu_parity.py",
+    "test_gpu_split.py",
     "test_gpu_offgrid.py",
     "test_gpu_sinc.py",
     "test_gpu_autograd.py",

@@ -304,6 +304,11 @@ int main()
                  opts(FD_VARIANT_TBLOCK, 0, 32, 4, 3), true);
     forward_case("so2 T4", g2o, 31, centre_src(g2o, 9), rec_line(g2o, 5, 9), opts(FD_VARIANT_TBLOCK, 0, 0, 0, 4),
                  true);
+    forward_case("so4 split", g4, 33, centre_src(g4, 15), Pts(), opts(FD_VARIANT_SPLIT, 9), true);
+    forward_case("so2 split receivers", g2o, 31, centre_src(g2o, 9), rec_line(g2o, 5, 9), opts(FD_VARIANT_SPLIT, 8),
+                 true);
+    forward_case("so8 split offgrid sources", g3, 24, scattered(g3, 40, 0, 21), Pts(), opts(FD_VARIANT_SPLIT, 17),
+                 true);
     const fd_grid g16 = grid({48, 40, 46}, 16);
     forward_case("so16 stream", g16, 20, centre_src(g16, 12), rec_line(g16, 9, 12), opts(FD_VARIANT_STREAM), true);
     const fd_grid g2 = grid({60, 70}, 4), g1 = grid({100}, 2, 0);

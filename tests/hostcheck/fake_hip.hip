@@ -253,7 +253,21 @@ void check_sweep(const Ctx &c, const KInfo &k, const SweepArgs &a, int ps_kernel
     const int rows = NW * PY, cr = rows - 2 * M * (T - 1), cc = 64 - 2 * M * (T - 1);
     CHECK(cr > 0 && cc > 0, "no core for M %d T %d rows %d", M, T, rows);
     CHECK(a.lx >= 1 && a.lx <= fdw::kMaxLx, "chunk %d", a.lx);
-    CHECK(a.ntx == (a.nx + a.lx - 1) / a.lx, "ntx %d for nx %d lx %d", a.ntx, a.nx, a.lx);
+    if (a.xstride > 0) {
+        // chunks placed at xoff + bx xstride (the inverted trapezoids of a split pass)
+        CHECK(a.split == 0 && T == 1 && a.xoff >= 0 && a.ntx >= 1 && a.xoff + (a.ntx - 1) * a.xstride < a.nx,
+              "placed chunks: xoff %d stride %d ntx %d nx %d", a.xoff, a.xstride, a.ntx, a.nx);
+        CHECK(a.xstride == a.xoff + M && a.lx == 2 * M, "gap chunks: lx %d xoff %d stride %d", a.lx, a.xoff,
+              a.xstride);
+    } else {
+        CHECK(a.xoff == 0, "chunk offset %d without a stride", a.xoff);
+        CHECK(a.ntx == (a.nx + a.lx - 1) / a.lx, "ntx %d for nx %d lx %d", a.ntx, a.nx, a.lx);
+    }
+    if (a.split) {
+        CHECK(T == 2 && MODE == fdw::kPlain && a.rec.cnt <= fdw::kStageMin && (a.rec.cnt == 0 || a.ps == 0) &&
+                  a.ntx >= 2 && a.lx >= 2 * M + 1,
+              "split pass: T %d mode %d receivers %d staged %d ntx %d lx %d", T, MODE, a.rec.cnt, a.ps, a.ntx, a.lx);
+    }
     CHECK(a.nty == (a.ny + cr - 1) / cr, "nty %d for ny %d core rows %d", a.nty, a.ny, cr);
     CHECK(a.ntz == (a.nz + cc - 1) / cc, "ntz %d for nz %d core cols %d", a.ntz, a.nz, cc);
     if (a.remap) {
@@ -324,7 +338,7 @@ void check_launch(const KInfo &k, dim3 grid, dim3 block, void **args)
         const int NW = k.tmpl[3];
         CHECK(block.x == (unsigned)(64 * NW), "block %u", block.x);
         CHECK(n >= 1 && in_dev(list, (size_t)n * sizeof(GroupEntry)), "table of %d entries outside the workspace", n);
-        CHECK(grid.x >= 1 && (int)grid.x <= total, "grid %u for %d tiles", grid.x, total);
+        CHECK(grid.x >= 1 && (int)grid.x <= (total + 7) / 8 * 8, "grid %u for %d tiles", grid.x, total);
         int next = 0;
         for (int e = 0; e < n; ++e) {
             c.entry = e;

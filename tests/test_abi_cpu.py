@@ -34,6 +34,17 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) == set(L.SYMBOLS)
 
 
+def test_binding_mirrors_every_header_constant():
+    """Every FD_* integer constant of the header has the same value in the binding."""
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(FD_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", text))
+    assert len(consts) > 25
+    for name, value in consts.items():
+        assert hasattr(L, name), name
+        assert getattr(L, name) == int(value), name
+    assert L.FD_NOALLOC_SCRATCH_BYTES == 64 << 20
+
+
 def test_version_and_strerror():
     assert L.fd_version() == 100
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):

@@ -58,7 +58,8 @@ def test_tuned_configuration_is_exact_and_used_by_automatic_plans(tmp_path, monk
     assert torch.equal(auto2["rec"], base2["rec"])
 
 
-def test_tuner_keeps_fixed_fields():
+def test_tuner_keeps_fixed_fields(tmp_path, monkeypatch):
+    monkeypatch.setenv("FD_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))  # not the committed cache
     v, h, so, nt, dt, src, rec, amp = case((40, 36, 70), so=4)
     tuned = api.autotune(tuple(v.shape), h, so, dt, sponge=6, vref=4500.0, variant=L.FD_VARIANT_TBLOCK,
                          tblock=2)

@@ -31,8 +31,9 @@ def hostcheck_exe(tmp_path_factory):
     return mod.build(str(tmp_path_factory.mktemp("hostcheck")), jobs=min(8, os.cpu_count() or 1))
 
 
-def test_host_code_is_clean_under_sanitizers(hostcheck_exe):
+def test_host_code_is_clean_under_sanitizers(hostcheck_exe, tmp_path):
     env = dict(os.environ)
+    env["FD_AUTOTUNE_CACHE"] = str(tmp_path / "tune.txt")  # the driver's tuner call writes here
     # the library keeps its lane streams for the life of the process by design
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:halt_on_error=1"
     env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
