@@ -335,6 +335,58 @@ int main()
         const fd_grid big = grid({160, 160, 160}, 8);
         noalloc_case("too large", big, 4, centre_src(big, 12), Pts(), opts(), FD_ESCRATCH);
     }
+    // seeded random draws over the planner's options (rank, ragged extents,
+    // order, variant, tile, chunk, points on and between nodes, steps); a
+    // draw whose kernel is not compiled returns FD_EUNSUPPORTED
+    {
+        uint32_t r = 12345u;
+        auto rnd = [&r](int n) {
+            r = r * 1664525u + 1013904223u;
+            return (int)((r >> 8) % (uint32_t)n);
+        };
+        static const int shapes[][2] = {{4, 8}, {2, 16}, {4, 4}, {8, 4}, {16, 2}, {8, 2}, {2, 8}};
+        static const int variants[] = {FD_VARIANT_STREAM, FD_VARIANT_TBLOCK, FD_VARIANT_SPLIT, 0};
+        int ok = 0, unsupported = 0;
+        for (int it = 0; it < 120; ++it) {
+            const int nd = 1 + (rnd(6) < 4 ? 2 : rnd(2));
+            const int so = 2 * (1 + rnd(8)), M = so / 2;
+            std::vector<int> n;
+            for (int a = 0; a < nd; ++a) n.push_back(2 * M + 1 + rnd(nd == 1 ? 250 : 60));
+            fd_grid g = grid(n, so, rnd(3) == 0 ? 0 : 1 + rnd(std::max(1, n[0] / 4)));
+            for (int a = 0; a < nd; ++a)
+                if (2 * g.sponge > n[a]) g.sponge = 0;
+            if (rnd(5) == 0) g.h[nd - 1] = 12.5;
+            fd_options o = opts(variants[rnd(4)]);
+            if (o.variant == FD_VARIANT_TBLOCK) o.tblock = 2 + rnd(3);
+            if (o.variant && rnd(10) < 7) {
+                static const int lxs[] = {0, 0, 7, 13, 32, 64};
+                const int k = rnd(7);
+                o.tile[0] = lxs[rnd(6)];
+                o.tile[1] = shapes[k][0] * shapes[k][1];
+                o.tile[2] = shapes[k][0];
+            }
+            const int64_t nt = 1 + rnd(40);
+            const bool between = rnd(5) < 2;
+            Pts src = between ? scattered(g, rnd(4), 0, 100 + it) : Pts();
+            if (!between && rnd(2)) src = centre_src(g, n.back() / 2);
+            Pts rec = (rnd(5) < 2) ? scattered(g, rnd(12), rnd(4) == 0 ? 2 : 0, 200 + it) : rec_line(g, 1 + rnd(9), 0);
+            const fd_time t{nt, stable_dt(g)};
+            const int64_t N = points(g);
+            Buf v(N * 4), amp((size_t)nt * std::max(src.p.n, 1) * 4), out((size_t)nt * std::max(rec.p.n, 1) * 4),
+                st(2 * N * 4);
+            for (int64_t i = 0; i < N; ++i) v.f()[i] = 2000.0f;
+            src.p.amp = amp.f();
+            const size_t ws = fd_workspace_size(&g, &t, &src.p, &rec.p, &o, FD_OP_FORWARD);
+            Buf w(ws);
+            const int rc = fd_forward(&g, &t, v.f(), &src.p, &rec.p, rec.p.n ? out.f() : nullptr, st.f(), w.p, ws, &o,
+                                      nullptr);
+            if (rc == FD_OK) ++ok;
+            else if (rc == FD_EUNSUPPORTED) ++unsupported;
+            else expect(rc, FD_OK, "random draw " + std::to_string(it));
+        }
+        std::printf("random draws: %d ran, %d not compiled\n", ok, unsupported);
+        expect(ok >= 60 ? FD_OK : -100, FD_OK, "random draws mostly compiled");
+    }
     // adjoint, gradients (checkpointed and whole time axis), vjp, Born
     adjoint_case("so8", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM));
     adjoint_case("so4 T2 offgrid", g4, 24, scattered(g4, 2, 0, 9), scattered(g4, 30, 0, 10),
