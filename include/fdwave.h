@@ -96,6 +96,10 @@ extern "C" {
 #define FD_EUNSUPPORTED (-8)  /* no compiled kernel for the requested options */
 #define FD_ESCRATCH (-9)      /* fd_forward_noalloc: the call needs more scratch than
                                  FD_NOALLOC_SCRATCH_BYTES */
+#define FD_ESYNC (-10)        /* FD_VARIANT_WAVE: a workgroup waited too long for its
+                                 neighbours (its launch did not run all workgroups at
+                                 once, e.g. the device was shared); the outputs are
+                                 undefined */
 
 /* ------------------------------------------------------------------ variants */
 #define FD_VARIANT_AUTO 0    /* autotuner / cached choice */
@@ -113,6 +117,23 @@ extern "C" {
                                 computed twice.  Passes with more than 32 receiver
                                 entries use TBLOCK's overlapped chunks.  tblock must
                                 be 0 or 2. */
+#define FD_VARIANT_WAVE 5    /* time-blocked, two levels per pass, without redundant
+                                halos (paper Secs. 5.2-5.5: each tile computes every
+                                level on its own points only): a workgroup owns a
+                                (y, z) tile of the whole x axis, level 2 trails level 1
+                                by M + E planes, and level 2 reads level 1 on the ring
+                                around its tile from the neighbouring workgroups once
+                                their progress counters show it stored (device-coherent
+                                exchange through the pass's u^{n+1} field).  tile[0] is
+                                ignored (the whole axis), tile[1] / tile[2] choose the
+                                tile's rows and rows per thread; tblock must be 0 or 2.
+                                All of a pass's workgroups must fit on the device at once
+                                (FD_EUNSUPPORTED otherwise); the call waits for its
+                                passes to finish and returns FD_ESYNC if a wait ran out.
+                                Plain forward and adjoint passes only: gradient and Born
+                                passes, passes whose point tables are injected or recorded
+                                separately, batches and single-step tails use the other
+                                variants' kernels. */
 
 /* ------------------------------------------------------------------ flags */
 #define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */

@@ -25,6 +25,7 @@ FD_EHIP = -6
 FD_ENONFINITE = -7
 FD_EUNSUPPORTED = -8
 FD_ESCRATCH = -9
+FD_ESYNC = -10
 
 FD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -33,6 +34,7 @@ FD_VARIANT_NAIVE = 1
 FD_VARIANT_STREAM = 2
 FD_VARIANT_TBLOCK = 3
 FD_VARIANT_SPLIT = 4
+FD_VARIANT_WAVE = 5
 
 FD_FLAG_NO_CFL_CHECK = 1
 FD_FLAG_CHECK_FINITE = 2

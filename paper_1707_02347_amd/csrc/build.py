@@ -47,6 +47,15 @@ def configs():
     return out
 
 
+def wave_configs():
+    """(M, PY, NW) tuples of every W(...) entry in fd_stream_configs.h."""
+    text = open(os.path.join(HERE, "fd_stream_configs.h")).read()
+    out = [tuple(int(g) for g in m.groups()) for m in re.finditer(r"W\((\d+),\s*(\d+),\s*(\d+)\)", text)]
+    if len(set(out)) != len(out):
+        raise RuntimeError("duplicate wave configuration in fd_stream_configs.h")
+    return out
+
+
 def _write_if_changed(path, text):
     if os.path.exists(path) and open(path).read() == text:
         return
@@ -69,17 +78,32 @@ def generate():
         path = os.path.join(GEN, name + ".hip")
         _write_if_changed(path, text)
         paths.append(path)
+    wnames = []
+    for cfg in wave_configs():
+        name = "kWave_%d_%d_%d" % cfg
+        wnames.append(name)
+        args = "%d, %d, %d" % cfg
+        text = ('// generated from fd_stream_configs.h\n#include "%s/fd_wave.h"\n#include "%s/fd_stream_entry.h"\n'
+                "namespace fdw {\nextern WaveEntry %s;\nWaveEntry %s = {%s, &wave_launch<%s>, &wave_occupancy<%s>};\n"
+                "}  // namespace fdw\n" % (HERE, HERE, name, name, args, args, args))
+        path = os.path.join(GEN, name + ".hip")
+        _write_if_changed(path, text)
+        paths.append(path)
     reg = ['// generated from fd_stream_configs.h', '#include "%s/fd_stream_entry.h"' % HERE, "namespace fdw {"]
     reg += ["extern StreamEntry %s;" % n for n in names]
+    reg += ["extern WaveEntry %s;" % n for n in wnames]
     reg += ["static const StreamEntry *const kRegistry[] = {"] + ["    &%s," % n for n in names] + ["};"]
+    reg += ["static const WaveEntry *const kWaveRegistry[] = {"] + ["    &%s," % n for n in wnames] + ["};"]
     reg += ["const StreamEntry *const *stream_registry(int *count)", "{",
             "    *count = (int)(sizeof(kRegistry) / sizeof(kRegistry[0]));", "    return kRegistry;", "}",
+            "const WaveEntry *const *wave_registry(int *count)", "{",
+            "    *count = (int)(sizeof(kWaveRegistry) / sizeof(kWaveRegistry[0]));", "    return kWaveRegistry;", "}",
             "}  // namespace fdw", ""]
     path = os.path.join(GEN, "fd_registry.hip")
     _write_if_changed(path, "\n".join(reg))
     paths.append(path)
     for f in os.listdir(GEN):  # sources of configurations no longer listed
-        if f.startswith("kEntry_") and os.path.join(GEN, f) not in paths:
+        if f.startswith(("kEntry_", "kWave_")) and os.path.join(GEN, f) not in paths:
             os.remove(os.path.join(GEN, f))
     return paths
 
@@ -94,7 +118,7 @@ def _compile(src: str) -> str:
     deps = [src] + [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith(".h")]
     if os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps):
         return obj
-    kernel = os.path.basename(src).startswith("kEntry")
+    kernel = os.path.basename(src).startswith(("kEntry", "kWave"))
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     if kernel:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
@@ -122,7 +146,7 @@ def build(jobs: int | None = None, verbose: bool = False, clean: bool = False) -
                 os.remove(os.path.join(BUILD, f))
     srcs = sources()
     # longest compiles first: generated kernel files
-    srcs.sort(key=lambda p: (0 if os.path.basename(p).startswith("kEntry") else 1, p))
+    srcs.sort(key=lambda p: (0 if os.path.basename(p).startswith(("kEntry", "kWave")) else 1, p))
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -98,6 +98,37 @@ bool stream_has_group(const KernelKey &k, bool iso)
     return e && (e->flags & 2) && (iso || (e->flags & 1));
 }
 
+const WaveEntry *find_wave(int M, int PY, int NW)
+{
+    int n = 0;
+    const WaveEntry *const *reg = wave_registry(&n);
+    for (int i = 0; i < n; ++i)
+        if (reg[i]->M == M && reg[i]->PY == PY && reg[i]->NW == NW) return reg[i];
+    return nullptr;
+}
+
+bool wave_has(int M, int PY, int NW) { return find_wave(M, PY, NW) != nullptr; }
+
+bool launch_wave(int M, int PY, int NW, const SweepArgs &a, hipStream_t s)
+{
+    const WaveEntry *e = find_wave(M, PY, NW);
+    return e && e->launch(a, s);
+}
+
+int wave_occupancy(int M, int PY, int NW, bool iso)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(M, PY, NW, iso ? 1 : 0);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const WaveEntry *e = find_wave(M, PY, NW);
+    const int n = e ? e->occupancy(iso) : 0;
+    cache[key] = n;
+    return n;
+}
+
 int stream_core_rows(const KernelKey &k) { return k.NW * k.PY - 2 * k.M * (k.T - 1); }
 int stream_core_cols(const KernelKey &k) { return 64 - 2 * k.M * (k.T - 1); }
 
@@ -316,6 +347,9 @@ struct Layout {
     TableBufs src{}, rec{};
     float *vstat = nullptr;
     double *rpart = nullptr;
+    uint64_t *prog = nullptr;       // progress counters of passes without redundant halos
+    int *err = nullptr;             // their error word
+    int nprog = 0;
     // gradient
     float *ckpt = nullptr;          // [nck][2][N]
     int nck = 0;
@@ -362,6 +396,10 @@ Layout layout(void *ws, const Dims &d, int64_t nt, const PtsSpec &S, const PtsSp
     L.rec = carve_table(cv, d.nx, R, nt);
     L.vstat = cv.take<float>(3 * kStatBlocks);
     L.rpart = cv.take<double>(kStatBlocks);
+    // one counter per tile of the smallest compiled tile (8 rows)
+    L.nprog = ((d.nz + 63) / 64) * ((d.ny + 7) / 8);
+    L.prog = cv.take<uint64_t>((size_t)L.nprog * kWaveProgStride);
+    L.err = cv.take<int>(64);
     if (op == FD_OP_BORN) L.seg = cv.take<float>(d.Np);  // the background's second difference
     if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
         L.nck = nt > 0 ? (int)((nt + K - 1) / K) : 0;
@@ -396,6 +434,7 @@ struct Plan {
     bool alt;
     int loads;        // cache policy of once-per-step loads: -1 automatic, 0 keep, 1 stream
     bool split = false;  // two-level plain passes split into trapezoids along x
+    bool wave = false;   // two-level plain passes without redundant halos (fd_wave.h)
 };
 
 std::mutex g_tune_mu;
@@ -510,6 +549,45 @@ KernelKey default_key(const Dims &d, int T)
     return KernelKey{d.M, 1, 8, 4, kPlain};
 }
 
+// Tiles of a pass without redundant halos: 64 columns by rows of y.
+int wave_tiles(const Dims &d, int rows) { return ((d.nz + 63) / 64) * ((d.ny + rows - 1) / rows); }
+
+// FD_VARIANT_WAVE: the tile shape (tile[1] rows of tile[2] per thread, or the
+// first compiled of a preference list), admitted only if every tile's
+// workgroup can be resident at once -- a pass's workgroups wait for their
+// neighbours, so all of them must run together.
+int wave_plan(const Dims &d, const fd_options &eff, Plan &p)
+{
+    if (eff.tblock != 0 && eff.tblock != 2) return FD_EINVAL;
+    const bool iso = grid_iso(d);
+    // measured at 512^3 (so 8 / so 16): 2 x 8 302 / 246 GPts/s, 2 x 4 296 / -,
+    // 1 x 16 279 / 233, 4 x 4 239 / 156
+    static const int shapes[][2] = {{2, 8}, {2, 4}, {1, 16}, {4, 4}};
+    int PY = 0, NW = 0;
+    if (eff.tile[1] > 0 || eff.tile[2] > 0) {
+        PY = eff.tile[2] > 0 ? eff.tile[2] : 4;
+        const int rows = eff.tile[1] > 0 ? eff.tile[1] : 16;
+        if (rows % PY) return FD_EUNSUPPORTED;
+        NW = rows / PY;
+        if (!wave_has(d.M, PY, NW)) return FD_EUNSUPPORTED;
+    } else {
+        for (auto &sh : shapes)
+            if (wave_has(d.M, sh[0], sh[1])) {
+                PY = sh[0];
+                NW = sh[1];
+                break;
+            }
+        if (!PY) return FD_EUNSUPPORTED;
+    }
+    const int64_t resident = (int64_t)wave_occupancy(d.M, PY, NW, iso) * device_cus();
+    if (wave_tiles(d, PY * NW) > resident) return FD_EUNSUPPORTED;
+    p.key = KernelKey{d.M, 2, PY, NW, kPlain};
+    p.lx = d.nx;
+    p.variant = FD_VARIANT_WAVE;
+    p.wave = true;
+    return FD_OK;
+}
+
 int make_plan(const Dims &d, const fd_options *o, Plan &p)
 {
     fd_options eff{};
@@ -528,9 +606,11 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
             it != g_tune.end() &&
             (it->second.variant == FD_VARIANT_NAIVE ||
              (it->second.tile[2] > 0 && it->second.tile[1] % it->second.tile[2] == 0 &&
-              stream_has(KernelKey{d.M, std::max(it->second.tblock, 1), it->second.tile[2],
-                                   it->second.tile[1] / it->second.tile[2], kPlain},
-                         grid_iso(d))));
+              (it->second.variant == FD_VARIANT_WAVE
+                   ? wave_has(d.M, it->second.tile[2], it->second.tile[1] / it->second.tile[2])
+                   : stream_has(KernelKey{d.M, std::max(it->second.tblock, 1), it->second.tile[2],
+                                          it->second.tile[1] / it->second.tile[2], kPlain},
+                                grid_iso(d)))));
         if (usable) {
             const fd_options &t = it->second;
             eff.variant = t.variant;
@@ -550,6 +630,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         p.lx = d.nx;
         return FD_OK;
     }
+    if (eff.variant == FD_VARIANT_WAVE) return wave_plan(d, eff, p);
     if (eff.variant != FD_VARIANT_STREAM && eff.variant != FD_VARIANT_TBLOCK && eff.variant != FD_VARIANT_SPLIT)
         return FD_EINVAL;
     int T = 1;
@@ -886,6 +967,13 @@ struct Exec {
         launch_stream(k, a, s);
         FDW_HIP(hipGetLastError());
     }
+    // a pass without redundant halos (issued immediately only: its
+    // workgroups wait for each other, so it is never merged into a batch)
+    void wave(const KernelKey &k, const SweepArgs &a)
+    {
+        if (rec || !launch_wave(k.M, k.PY, k.NW, a, s)) throw Status{FD_EUNSUPPORTED};
+        FDW_HIP(hipGetLastError());
+    }
     template <class F>
     void call(F f)
     {
@@ -917,6 +1005,7 @@ struct Ctx {
     std::vector<int32_t> hxs, hxr;  // host copies of the point tables' plane pointers
     int ran_T = 0;    // deepest time block a pass of this call used (0: none yet)
     bool ran_split = false;  // a pass of this call ran split along x
+    uint32_t wave_epoch = 0;  // passes without redundant halos issued so far
 };
 
 // Whether a pass walks its point entries staged in LDS: a configuration that
@@ -1174,12 +1263,47 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // receivers recorded after the pass need its output level in memory
         bool isep = iheavy, rsep = iheavy || heavy_table(c, a.rec);
         const bool iso = c.base.w.iso != 0;
+        // two levels without redundant halos: plain passes with both steps
+        // left, issued immediately, whose point tables need no separate route
+        // (such tables and single-step tails take the passes below)
+        if (c.plan.wave && !c.ex.rec && so.mode == kPlain && !isep && !rsep && nsteps - s >= 2) {
+            const KernelKey &k = c.plan.key;
+            a.u0 = st.cur;
+            a.um = st.prev;
+            a.o1 = st.spare[0];  // u^{n+2}
+            a.o2 = st.spare[1];  // u^{n+1}: the exchanged level
+            a.lx = d.nx;
+            a.ntx = 1;
+            a.ntz = (d.nz + 63) / 64;
+            a.nty = (d.ny + k.NW * k.PY - 1) / (k.NW * k.PY);
+            if (a.ntz * a.nty > c.L.nprog) throw Status{FD_EUNSUPPORTED};
+            a.remap = c.plan.remap ? 1 : 0;
+            a.prog = c.L.prog;
+            a.err = c.L.err;
+            a.epoch = ++c.wave_epoch;
+            if (a.epoch == 1) {
+                // counters start below every epoch; no error yet
+                uint64_t *prog = c.L.prog;
+                int *err = c.L.err;
+                const int64_t nb = (int64_t)c.L.nprog * kWaveProgStride * 8;
+                c.ex.call([prog, err, nb](hipStream_t s) {
+                    hipError_t e = launch_zero(prog, nb, s);
+                    return e == hipSuccess ? launch_zero(err, 256, s) : e;
+                });
+            }
+            c.ex.wave(k, a);
+            swap_in(st, a.o1, a.o2);
+            c.ran_T = std::max(c.ran_T, 2);
+            s += 2;
+            continue;
+        }
         const SweepArgs a0 = a;
         KernelKey k{};
         float *o1 = nullptr, *o2 = nullptr;
         auto plan_pass = [&]() {
             a = a0;
-            const int T = (!rsep && nsteps - s >= c.plan.key.T) ? c.plan.key.T : 1;
+            // (a plan of passes without halos runs its other passes single-level)
+            const int T = (!rsep && nsteps - s >= c.plan.key.T && !c.plan.wave) ? c.plan.key.T : 1;
             const int kmode = isep ? (int)kPlain : so.mode;
             k = (T == c.plan.key.T && kmode == kPlain) ? c.plan.key : key_for(c.plan.key, T, kmode, iso);
             if (k.T != T) k = key_for(c.plan.key, 1, kmode, iso);
@@ -1352,11 +1476,25 @@ void record_last(const Ctx &c)
     g_last.tile[1] = p.key.NW * p.key.PY;
     g_last.tile[2] = p.key.PY;
     g_last.tblock = c.ran_T > 0 ? c.ran_T : p.key.T;
-    if ((p.variant == FD_VARIANT_TBLOCK || p.variant == FD_VARIANT_SPLIT) && c.ran_T == 1)
+    if ((p.variant == FD_VARIANT_TBLOCK || p.variant == FD_VARIANT_SPLIT || p.variant == FD_VARIANT_WAVE) &&
+        c.ran_T == 1)
         g_last.variant = FD_VARIANT_STREAM;
+    else if (p.variant == FD_VARIANT_WAVE && c.wave_epoch == 0)
+        g_last.variant = FD_VARIANT_TBLOCK;
     else if (p.variant == FD_VARIANT_SPLIT && !c.ran_split)
         g_last.variant = FD_VARIANT_TBLOCK;
     g_last_valid = true;
+}
+
+// After a call that ran passes without redundant halos: wait for them and
+// report a wait that ran out (the outputs are then undefined).
+int wave_status(const Ctx &c)
+{
+    if (c.wave_epoch == 0) return FD_OK;
+    int e = 0;
+    FDW_HIP(hipMemcpyAsync(&e, c.L.err, sizeof e, hipMemcpyDeviceToHost, c.s));
+    FDW_HIP(hipStreamSynchronize(c.s));
+    return e ? FD_ESYNC : FD_OK;
 }
 
 template <class F>
@@ -1516,6 +1654,7 @@ int forward_impl(const fd_grid *grid, const fd_time *time, const float *v, const
     if (rc) return rc;
     fwd_issue(j);
     record_last(j.c);
+    if ((rc = wave_status(j.c))) return rc;
     if (j.flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, j.c.nt * j.nr, j.c.s);
     return FD_OK;
 }
@@ -1698,6 +1837,7 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v, const f
             FDW_HIP(launch_repitch(lam_state + c.d.N, c.d.nz, st.prev, c.d.nzp, rows, c.d.nz, c.s));
         }
         record_last(c);
+        if ((rc = wave_status(c))) return rc;
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(src_out, c.nt * ns, c.s);
         return FD_OK;
     });
@@ -1774,6 +1914,7 @@ int fd_born(const fd_grid *grid, const fd_time *time, const float *v, const floa
         }
         gather_traces(c, c.L.rec, nr, pb.rec.cnt, rec_out, 1.0f);
         record_last(c);
+        if ((rc = wave_status(c))) return rc;
         if (flags & FD_FLAG_CHECK_FINITE) return check_finite_traces(rec_out, c.nt * nr, c.s);
         return FD_OK;
     });
@@ -1975,7 +2116,7 @@ int gradient_impl(const fd_grid *grid, const fd_time *time, const float *v, cons
     grad_issue(j);
     if (!y && misfit) *misfit = grad_misfit(j);
     record_last(j.c);
-    return FD_OK;
+    return wave_status(j.c);
 }
 
 }  // namespace
@@ -2054,6 +2195,13 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
                 push(variant, lx, sh[0] * sh[1], sh[0], depth);
             }
         }
+    }
+    // two levels without redundant halos, where all tiles fit the device at once
+    if (!fixed.variant || fixed.variant == FD_VARIANT_WAVE) {
+        static const int wshapes[][2] = {{2, 8}, {2, 4}, {1, 16}, {4, 4}};
+        for (auto &sh : wshapes)
+            if (wave_has(d.M, sh[0], sh[1]) && (!fixed.tblock || fixed.tblock == 2))
+                push(FD_VARIANT_WAVE, 0, sh[0] * sh[1], sh[0], 2);
     }
     return out;
 }
@@ -2151,11 +2299,13 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
             FDW_HIP(launch_zero(st.cur, d.Np * 4, s));
             FDW_HIP(launch_zero(st.prev, d.Np * 4, s));
             const int64_t steps = std::max<int64_t>(tt.nt, p.key.T) / p.key.T * p.key.T;
+            c.wave_epoch = 0;  // a candidate's first pass without halos clears the counters
             advance(c, st, 0, steps, StepOpts{});  // warm-up
             FDW_HIP(hipEventRecord(e0, s));
             advance(c, st, 0, steps, StepOpts{});
             FDW_HIP(hipEventRecord(e1, s));
             FDW_HIP(hipEventSynchronize(e1));
+            if (wave_status(c) != FD_OK) continue;  // a wait ran out: not a valid timing
             float ms = 0.0f;
             FDW_HIP(hipEventElapsedTime(&ms, e0, e1));
             const float per_step = ms / (float)steps;

@@ -108,6 +108,13 @@ struct SweepArgs {
     // second phase, a single-level pass over the 2M planes around each shared
     // end, fills level 2 in those gaps.
     int split;
+    // Passes without redundant halos (fd_wave.h): per-tile progress counters
+    // ((epoch << 32) | iterations completed), the pass's epoch (distinct for
+    // every pass of a sweep; the counters start at 0), and the error word a
+    // wait that runs out sets.
+    uint64_t *prog;
+    int *err;
+    uint32_t epoch;
 };
 
 // Point entries x time levels a workgroup can stage in LDS, the configurations
@@ -172,6 +179,19 @@ int stream_core_cols(const KernelKey &key);
 // whether its grouped batch kernel is.
 bool stream_has(const KernelKey &key, bool iso);
 bool stream_has_group(const KernelKey &key, bool iso);
+
+// Two-level passes without redundant halos (fd_wave.h): whether a tile shape
+// (PY rows per thread, NW waves) is compiled for radius M, its launcher (one
+// workgroup per (y, z) tile of a.ntz x a.nty) and its resident workgroups per
+// CU (0 if not compiled).
+bool wave_has(int M, int PY, int NW);
+// Spacing of the progress counters in uint64 elements: one counter per 256
+// bytes, so no two workgroups' counters share a cache line (counters packed
+// into a few lines, stored and polled by every workgroup each iteration,
+// serialised those accesses and cut the 512^3 so-8 rate from 260 to 81 GPts/s).
+constexpr int kWaveProgStride = 32;
+bool launch_wave(int M, int PY, int NW, const SweepArgs &a, hipStream_t s);
+int wave_occupancy(int M, int PY, int NW, bool iso);
 
 // Naive (untiled) kernels.
 hipError_t launch_naive_step(int M, const SweepArgs &a, hipStream_t s);  // form from a.w.iso

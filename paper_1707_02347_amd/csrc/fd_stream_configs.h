@@ -54,3 +54,10 @@
     X(8, 1, 4, 8, 0, FDW_AG) X(8, 1, 2, 16, 0, 0) X(8, 1, 8, 4, 1, FDW_AG)                 \
     X(8, 1, 8, 4, 2, FDW_AG) X(8, 1, 4, 4, 1, FDW_AG) X(8, 1, 4, 4, 2, FDW_AG)             \
     X(8, 2, 4, 8, 0, FDW_AG) X(8, 2, 4, 8, 1, FDW_G) X(8, 1, 4, 4, 3, FDW_A)
+
+// Two-level passes without redundant halos (fd_wave.h): W(M, PY, NW), tiles of
+// 64 columns x NW*PY rows; both Laplacian forms.
+#define FDW_WAVE_CONFIGS(W)                                                                \
+    W(1, 4, 4) W(1, 2, 8) W(2, 4, 4) W(2, 2, 8) W(3, 4, 4) W(3, 2, 8) W(4, 4, 4) W(4, 2, 8) \
+    W(4, 2, 4) W(5, 4, 4) W(5, 2, 8) W(6, 4, 4) W(6, 2, 8) W(7, 4, 4) W(7, 2, 8) W(8, 4, 4) \
+    W(8, 2, 8) W(8, 2, 4) W(4, 1, 16) W(8, 1, 16)

@@ -18,4 +18,13 @@ struct StreamEntry {
 // All compiled entries (generated).
 const StreamEntry *const *stream_registry(int *count);
 
+// Two-level passes without redundant halos: one entry per W(...) line of
+// fd_stream_configs.h (both Laplacian forms).
+struct WaveEntry {
+    int M, PY, NW;
+    bool (*launch)(const SweepArgs &a, hipStream_t s);
+    int (*occupancy)(bool iso);
+};
+const WaveEntry *const *wave_registry(int *count);
+
 }  // namespace fdw

@@ -17,6 +17,7 @@ os.environ.setdefault("FD_AUTOTUNE_CACHE", os.path.join(ROOT, "paper_1707_02347_
 ORDER = [
     "test_gpu_parity.py",
     "test_gpu_split.py",
+    "test_gpu_wave.py",
     "test_gpu_random_configs.py",
     "test_gpu_offgrid.py",
     "test_gpu_sinc.py",

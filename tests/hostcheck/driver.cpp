@@ -311,6 +311,13 @@ int main()
                  true);
     const fd_grid g16 = grid({48, 40, 46}, 16);
     forward_case("so16 stream", g16, 20, centre_src(g16, 12), rec_line(g16, 9, 12), opts(FD_VARIANT_STREAM), true);
+    // two levels without redundant halos: counters, epochs, tails and routes
+    forward_case("so8 wave", g3, 25, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_WAVE), true);
+    forward_case("so4 wave tile offgrid", g4, 33, scattered(g4, 3, 0, 22), scattered(g4, 20, 0, 23),
+                 opts(FD_VARIANT_WAVE, 0, 16, 2), true);
+    forward_case("so16 wave", g16, 20, centre_src(g16, 12), rec_line(g16, 9, 12), opts(FD_VARIANT_WAVE), true);
+    forward_case("so8 wave sinc receivers", g3, 20, centre_src(g3, 12), scattered(g3, 30, 4, 24),
+                 opts(FD_VARIANT_WAVE), false);
     const fd_grid g2 = grid({60, 70}, 4), g1 = grid({100}, 2, 0);
     forward_case("2-D so4", g2, 40, centre_src(g2, 20), rec_line(g2, 7, 5), opts(), true);
     forward_case("1-D so2", g1, 40, centre_src(g1, 30), Pts(), opts(), true);
@@ -345,7 +352,7 @@ int main()
             return (int)((r >> 8) % (uint32_t)n);
         };
         static const int shapes[][2] = {{4, 8}, {2, 16}, {4, 4}, {8, 4}, {16, 2}, {8, 2}, {2, 8}};
-        static const int variants[] = {FD_VARIANT_STREAM, FD_VARIANT_TBLOCK, FD_VARIANT_SPLIT, 0};
+        static const int variants[] = {FD_VARIANT_STREAM, FD_VARIANT_TBLOCK, FD_VARIANT_SPLIT, FD_VARIANT_WAVE, 0};
         int ok = 0, unsupported = 0;
         for (int it = 0; it < 120; ++it) {
             const int nd = 1 + (rnd(6) < 4 ? 2 : rnd(2));
@@ -356,7 +363,7 @@ int main()
             for (int a = 0; a < nd; ++a)
                 if (2 * g.sponge > n[a]) g.sponge = 0;
             if (rnd(5) == 0) g.h[nd - 1] = 12.5;
-            fd_options o = opts(variants[rnd(4)]);
+            fd_options o = opts(variants[rnd(5)]);
             if (o.variant == FD_VARIANT_TBLOCK) o.tblock = 2 + rnd(3);
             if (o.variant && rnd(10) < 7) {
                 static const int lxs[] = {0, 0, 7, 13, 32, 64};
@@ -389,6 +396,7 @@ int main()
     }
     // adjoint, gradients (checkpointed and whole time axis), vjp, Born
     adjoint_case("so8", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM));
+    adjoint_case("so8 wave", g3, 25, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_WAVE));
     adjoint_case("so4 T2 offgrid", g4, 24, scattered(g4, 2, 0, 9), scattered(g4, 30, 0, 10),
                  opts(FD_VARIANT_TBLOCK, 0, 0, 0, 2));
     gradient_case("so8 ckpt 7", g3, 30, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM, 0, 0, 0, 0, 0, 7),
@@ -423,6 +431,7 @@ int main()
         {{60, 70}, 4, 40, opts()},
         {{44, 40, 50}, 8, 27, opts(FD_VARIANT_TBLOCK, 0, 0, 0, 2)},
         {{42, 37, 45}, 4, 33, opts(FD_VARIANT_TBLOCK, 0, 32, 4, 3)},
+        {{44, 40, 50}, 8, 21, opts(FD_VARIANT_WAVE)},
     };
     for (uint32_t bf : {0u, (uint32_t)FD_BATCH_GRAPH}) {
         batch_case(bf ? "graph" : "direct", mix, false, bf, 0);

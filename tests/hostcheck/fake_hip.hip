@@ -152,7 +152,7 @@ struct KInfo {
     std::string name;  // demangled
     int tmpl[8] = {};
     int ntmpl = 0;
-    enum { kOther, kStream, kGrouped } kind = kOther;
+    enum { kOther, kStream, kGrouped, kWave } kind = kOther;
 };
 // registered from the objects' module constructors, which may run before this
 // file's globals are constructed: built on first use
@@ -318,6 +318,64 @@ void check_sweep(const Ctx &c, const KInfo &k, const SweepArgs &a, int ps_kernel
     }
 }
 
+// A two-level pass without redundant halos, kernel (M, PY, NW, ISO): one
+// workgroup per (y, z) tile over the whole x axis, every workgroup resident at
+// once (the stand-in's occupancy times 256 CUs), counters for every tile, and
+// an epoch that starts at 1 after the counters were cleared and then grows by
+// one per pass.
+std::map<const void *, uint32_t> &epochs()
+{
+    static std::map<const void *, uint32_t> *m = new std::map<const void *, uint32_t>();
+    return *m;
+}
+
+void check_wave(const Ctx &c, const KInfo &k, dim3 grid, dim3 block, const SweepArgs &a)
+{
+    const int M = k.tmpl[0], PY = k.tmpl[1], NW = k.tmpl[2];
+    CHECK(block.x == (unsigned)(64 * NW) && block.y == 1 && block.z == 1, "block %u", block.x);
+    CHECK(a.nx > 0 && a.ny > 0 && a.nz > 0 && a.nzp >= a.nz && a.nzp % 32 == 0 && a.sxy == (int64_t)a.ny * a.nzp,
+          "extents %d %d %d pitch %d", a.nx, a.ny, a.nz, a.nzp);
+    CHECK(a.ntz == (a.nz + 63) / 64 && a.nty == (a.ny + PY * NW - 1) / (PY * NW) && a.ntx == 1 && a.lx == a.nx,
+          "tiles %d x %d x %d (lx %d) for %d x %d x %d", a.ntz, a.nty, a.ntx, a.lx, a.nx, a.ny, a.nz);
+    CHECK(grid.x == (unsigned)(a.ntz * a.nty) && grid.y == 1 && grid.z == 1, "grid %u for %d tiles", grid.x,
+          a.ntz * a.nty);
+    CHECK(grid.x <= 2u * 256u, "grid %u beyond the resident workgroups", grid.x);
+    const size_t F = (size_t)a.nx * a.sxy * 4;
+    CHECK(in_dev(a.u0, F) && in_dev(a.um, F) && in_dev(a.q, F) && in_dev(a.o1, F) && in_dev(a.o2, F),
+          "a field outside the buffers");
+    CHECK(a.o1 != a.o2 && a.o1 != a.u0 && a.o1 != a.um && a.o2 != a.u0 && a.o2 != a.um,
+          "the pass writes over its inputs or one output twice");
+    CHECK(in_dev(a.px, (size_t)a.nx * 4) && in_dev(a.py, (size_t)a.ny * 4) && in_dev(a.pz, (size_t)a.nz * 4),
+          "sponge profiles outside the buffers");
+    CHECK(in_dev(a.prog, (size_t)a.ntz * a.nty * fdw::kWaveProgStride * 8) && in_dev(a.err, 4),
+          "counters outside the workspace");
+    CHECK(a.epoch >= 1, "epoch 0");
+    uint32_t &last = epochs()[a.prog];
+    CHECK(a.epoch == 1 || a.epoch == last + 1, "epoch %u after %u", a.epoch, last);
+    last = a.epoch;
+    CHECK(a.split == 0 && a.ps == 0 && a.xstride == 0 && a.xoff == 0, "split / staged / placed chunks");
+    check_table(c, a.inj, a.nx, a.sxy, true);
+    check_table(c, a.rec, a.nx, a.sxy, false);
+    for (int t = 1; t <= 2; ++t) {
+        const int64_t s = (int64_t)a.step0 + t - 1;
+        if (a.inj.cnt > 0) {
+            const int64_t row = a.abase + (int64_t)a.adir * s;
+            CHECK(row >= 0 && in_dev(a.amp + row * a.inj.stride, (size_t)a.inj.stride * 4),
+                  "level %d injects amplitude row %lld outside the buffer", t, (long long)row);
+        }
+        if (a.rec.cnt > 0) {
+            const int64_t row = a.rbase + (int64_t)a.rdir * s;
+            if (a.rec.etr)
+                CHECK(row >= 0 && in_dev(a.rec.etr + row * a.rec.cnt, (size_t)a.rec.cnt * 4),
+                      "level %d records entry row %lld outside the buffer", t, (long long)row);
+            else
+                CHECK(row >= 0 && in_dev(a.rec_out + row * a.rec.stride, (size_t)a.rec.stride * 4),
+                      "level %d records trace row %lld outside the buffer", t, (long long)row);
+        }
+    }
+    (void)M;
+}
+
 void check_launch(const KInfo &k, dim3 grid, dim3 block, void **args)
 {
     Ctx c{k.name.c_str(), -1};
@@ -330,6 +388,9 @@ void check_launch(const KInfo &k, dim3 grid, dim3 block, void **args)
               "grid %u for %d tiles", grid.x, a.ntx * a.nty * a.ntz);
         CHECK(a.ps == k.tmpl[7], "staged flag %d in kernel form %d", a.ps, k.tmpl[7]);
         check_sweep(c, k, a, k.tmpl[7]);
+    } else if (k.kind == KInfo::kWave) {
+        ++g_checked;
+        check_wave(c, k, grid, block, *reinterpret_cast<const SweepArgs *>(args[0]));
     } else if (k.kind == KInfo::kGrouped) {
         ++g_grouped;
         const GroupEntry *list = *reinterpret_cast<const GroupEntry *const *>(args[0]);
@@ -378,6 +439,7 @@ void __hipRegisterFunction(void **, const void *host, char *, const char *dev_na
     std::free(dm);
     if (k.name.rfind("void fdw::k_stream_grouped<", 0) == 0) k.kind = KInfo::kGrouped;
     else if (k.name.rfind("void fdw::k_stream<", 0) == 0) k.kind = KInfo::kStream;
+    else if (k.name.rfind("void fdw::k_wave<", 0) == 0) k.kind = KInfo::kWave;
     parse_template(k);
     kernels()[host] = k;
 }
@@ -433,7 +495,7 @@ hipError_t hipLaunchKernel(const void *fn, dim3 grid, dim3 block, void **args, s
     if (grid.x == 0 || block.x == 0 || block.x > 1024) fail("%s: grid %u block %u", it->second.name.c_str(), grid.x, block.x);
     const KInfo &k = it->second;
     // the arguments are only valid during the call: copy what the checks read
-    if (k.kind == KInfo::kStream) {
+    if (k.kind == KInfo::kStream || k.kind == KInfo::kWave) {
         SweepArgs a = *reinterpret_cast<const SweepArgs *>(args[0]);
         enqueue(S(s, "hipLaunchKernel"), [k, grid, block, a]() {
             void *ar[1] = {(void *)&a};

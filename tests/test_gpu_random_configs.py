@@ -1,5 +1,5 @@
 """Seeded random draws over the planner's options: grid rank and ragged
-extents, space order, variant (space-tiled, time-blocked T = 2..4, split),
+extents, space order, variant (space-tiled, time-blocked T = 2..4, split, without redundant halos),
 tile shape, chunk length, cache policy, sources and receivers on and between
 nodes, step count.  Every draw (draws of configurations that are not compiled
 are replaced by the next) must equal the untiled kernel bit for bit: traces and the final state
@@ -27,7 +27,7 @@ def draw(rng):
     shape = tuple(int(rng.integers(lo, lo + 60)) for _ in range(nd))
     if nd == 1:
         shape = (int(rng.integers(lo, 300)),)
-    variant = int(rng.choice([L.FD_VARIANT_STREAM, L.FD_VARIANT_TBLOCK, L.FD_VARIANT_SPLIT, 0]))
+    variant = int(rng.choice([L.FD_VARIANT_STREAM, L.FD_VARIANT_TBLOCK, L.FD_VARIANT_SPLIT, L.FD_VARIANT_WAVE, 0]))
     opts = dict(variant=variant)
     if variant == L.FD_VARIANT_TBLOCK:
         opts["tblock"] = int(rng.integers(2, 5))
