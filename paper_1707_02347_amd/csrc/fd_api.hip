@@ -561,8 +561,8 @@ int wave_plan(const Dims &d, const fd_options &eff, Plan &p)
     if (eff.tblock != 0 && eff.tblock != 2) return FD_EINVAL;
     const bool iso = grid_iso(d);
     // measured at 512^3 (so 8 / so 16): 2 x 8 302 / 246 GPts/s, 2 x 4 296 / -,
-    // 1 x 16 279 / 233, 4 x 4 239 / 156
-    static const int shapes[][2] = {{2, 8}, {2, 4}, {1, 16}, {4, 4}};
+    // 4 x 4 239 / 156 (1 x 16, dropped: 279 / 233)
+    static const int shapes[][2] = {{2, 8}, {2, 4}, {4, 4}};
     int PY = 0, NW = 0;
     if (eff.tile[1] > 0 || eff.tile[2] > 0) {
         PY = eff.tile[2] > 0 ? eff.tile[2] : 4;
@@ -2198,7 +2198,7 @@ std::vector<Candidate> candidates(const Dims &d, const fd_options &fixed)
     }
     // two levels without redundant halos, where all tiles fit the device at once
     if (!fixed.variant || fixed.variant == FD_VARIANT_WAVE) {
-        static const int wshapes[][2] = {{2, 8}, {2, 4}, {1, 16}, {4, 4}};
+        static const int wshapes[][2] = {{2, 8}, {2, 4}, {4, 4}};
         for (auto &sh : wshapes)
             if (wave_has(d.M, sh[0], sh[1]) && (!fixed.tblock || fixed.tblock == 2))
                 push(FD_VARIANT_WAVE, 0, sh[0] * sh[1], sh[0], 2);

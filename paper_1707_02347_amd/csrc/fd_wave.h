@@ -68,6 +68,13 @@ struct WaveKernel {
     static constexpr int E = wave_extra(M);
     static constexpr int Q = 2 * M + 1 + E;  // queue length of u^n and of level 1 along x
     static constexpr int QQ = M + E + 1;     // queue of q: level 1's plane down to level 2's
+    // The x loop is unrolled by U: phase PH of the unrolled body pushes into
+    // slot (queue length) + PH, so a queue's window of planes sits at slots
+    // [PH, PH + length) before that push and [PH + 1, PH + 1 + length) after
+    // it; the slots move back by U once per body (one register move per slot
+    // every U iterations instead of every iteration).
+    static constexpr int U = 4;
+    static constexpr int QX = Q + U, QQX = QQ + U;  // slots: the last push lands in Q + U - 1
     static constexpr int LW = RZ + 2 * M;    // LDS plane with its M-wide ring
     static constexpr int LH = RY + 2 * M;
     // the ring without its corners (the star stencil never reads them)
@@ -169,13 +176,13 @@ struct WaveKernel {
         if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) th.gaveup = true;
 
         // queues along x, entry 0 the oldest: u^n (qa) and level 1 (qb)
-        float qa[PY][Q], qb[PY][Q], qq[PY][QQ];
+        float qa[PY][QX], qb[PY][QX], qq[PY][QQX];
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
 #pragma unroll
-            for (int j = 0; j < Q; ++j) qa[r][j] = qb[r][j] = 0.0f;
+            for (int j = 0; j < QX; ++j) qa[r][j] = qb[r][j] = 0.0f;
 #pragma unroll
-            for (int j = 0; j < QQ; ++j) qq[r][j] = 0.0f;
+            for (int j = 0; j < QQX; ++j) qq[r][j] = 0.0f;
         }
         // planes 0 .. M-1 of u^n enter before the first iteration (i = M, level
         // 1 at plane 0); the queue then holds planes M - Q + j in entries j
@@ -186,17 +193,30 @@ struct WaveKernel {
             for (int r = 0; r < PY; ++r) qa[r][Q - M + j] = bload(rh, th.bo[r]);
         }
         const int ibeg = M, iend = a.nx + 2 * M + E;  // level 2's last plane nx - 1 at iend - 1
-        // Two prefetch slots, the loop unrolled by two: iteration i consumes
-        // slot i & 1 and first issues the loads of iteration i + 1 into the
-        // other, so no loaded register is ever copied (a copy would wait for
-        // the loads in flight).
+        // Two prefetch slots: iteration i consumes slot i & 1 and first issues
+        // the loads of iteration i + 1 into the other, so no loaded register
+        // is ever copied (a copy would wait for the loads in flight).
         uint64_t flag = poll(a, th);
         Pre p0, p1;
         load(a, th, p0, ibeg);
-        for (int i = ibeg; i < iend; i += 2) {
-            iteration(a, sm, th, qa, qb, qq, flag, p1, p0, i);
+        for (int i = ibeg; i < iend; i += U) {
+            iteration<0>(a, sm, th, qa, qb, qq, flag, p1, p0, i);
             if (i + 1 >= iend) break;
-            iteration(a, sm, th, qa, qb, qq, flag, p0, p1, i + 1);
+            iteration<1>(a, sm, th, qa, qb, qq, flag, p0, p1, i + 1);
+            if (i + 2 >= iend) break;
+            iteration<2>(a, sm, th, qa, qb, qq, flag, p1, p0, i + 2);
+            if (i + 3 >= iend) break;
+            iteration<3>(a, sm, th, qa, qb, qq, flag, p0, p1, i + 3);
+#pragma unroll
+            for (int r = 0; r < PY; ++r) {
+#pragma unroll
+                for (int j = 0; j < Q; ++j) {
+                    qa[r][j] = qa[r][j + U];
+                    qb[r][j] = qb[r][j + U];
+                }
+#pragma unroll
+                for (int j = 0; j < QQ; ++j) qq[r][j] = qq[r][j + U];
+            }
         }
     }
 
@@ -204,8 +224,9 @@ struct WaveKernel {
     // neighbours, so first wait until they have stored it, poll again for the
     // next iteration, issue iteration i + 1's loads into `next`, then compute
     // from `cur`.
+    template <int PH>
     __device__ static __forceinline__ void iteration(const SweepArgs &a, Smem &sm, Thread &th,
-                                                     float (&qa)[PY][Q], float (&qb)[PY][Q], float (&qq)[PY][QQ],
+                                                     float (&qa)[PY][QX], float (&qb)[PY][QX], float (&qq)[PY][QQX],
                                                      uint64_t &flag, Pre &next, const Pre &cur, int i)
     {
         wait_for(a, th, flag, i + 1);
@@ -215,7 +236,7 @@ struct WaveKernel {
         // loads issued after it complete only after it
         if (!__all(flag >= want_of(a, i + 2))) flag = poll(a, th);
         load(a, th, next, i + 1);
-        step(a, sm, th, qa, qb, qq, cur, i);
+        step<PH>(a, sm, th, qa, qb, qq, cur, i);
         // keep this iteration's stores ahead of the next iteration's loads in
         // issue order (the counter protocol relies on it)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -307,7 +328,7 @@ struct WaveKernel {
     // queue centre), up the level two below, then the point entries.
     template <int CJ>
     __device__ static __forceinline__ void update(const SweepArgs &a, const Thread &th,
-                                                  const float (&qq)[PY][Q], const float *S,
+                                                  const float (&qq)[PY][QX], const float *S,
                                                   const float (&up)[PY], const float (&qv)[PY], float pxv,
                                                   bool need, int step, int ib, int ie, float (&out)[PY])
     {
@@ -377,10 +398,13 @@ struct WaveKernel {
 
     // One iteration: publish both LDS planes, barrier, progress counter,
     // level 1 at c1 = i - M, level 2 at c2 = i - 2M - E.
+    template <int PH>
     __device__ static __forceinline__ void step(const SweepArgs &a, Smem &sm, const Thread &th,
-                                                float (&qa)[PY][Q], float (&qb)[PY][Q], float (&qq)[PY][QQ],
+                                                float (&qa)[PY][QX], float (&qb)[PY][QX], float (&qq)[PY][QQX],
                                                 const Pre &P, int i)
     {
+        static_assert(PH + Q < QX && PH + QQ < QQX, "a phase's push lands beyond the queue slots");
+        static_assert(PH + 1 + 2 * M < QX, "level 2's window beyond the queue slots");
         const int par = i & 1;
         const int c1 = i - M, c2 = i - 2 * M - E;
         float *S0 = sm.s0[par], *S1 = sm.s1[par];
@@ -392,17 +416,19 @@ struct WaveKernel {
                 S1[row * LW + col] = P.h1[s];
             }
         }
-        // own rows: u^n at c1 (queue entry Q - M before this iteration's push)
-        // and level 1 at c2 (entry M + 1 of its queue before the push)
+        // own rows: u^n at c1 (window entry Q - M before this iteration's
+        // push) and level 1 at c2 (entry M + 1 of its window before the push)
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
-            S0[(th.wv * PY + r + M) * LW + th.lane + M] = qa[r][Q - M];
-            S1[(th.wv * PY + r + M) * LW + th.lane + M] = qb[r][M + 1];
+            S0[(th.wv * PY + r + M) * LW + th.lane + M] = qa[r][PH + Q - M];
+            S1[(th.wv * PY + r + M) * LW + th.lane + M] = qb[r][PH + M + 1];
         }
         __syncthreads();
         // every wave has waited for this iteration's loads, issued after its
         // stores of iteration i - 2: those stores are complete
-        if (threadIdx.x == 0)
+        // (every second iteration: the readers' slack, M + E - 4 iterations,
+        // covers the extra one)
+        if (threadIdx.x == 0 && (PH & 1) == 0)
             __hip_atomic_store(a.prog + (int64_t)kWaveProgStride * th.tile, ((uint64_t)a.epoch << 32) | (uint32_t)(i - 1),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
@@ -410,16 +436,12 @@ struct WaveKernel {
         // u^n queue
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
-#pragma unroll
-            for (int j = 0; j + 1 < Q; ++j) qa[r][j] = qa[r][j + 1];
-            qa[r][Q - 1] = P.head[r];
-#pragma unroll
-            for (int j = 0; j + 1 < QQ; ++j) qq[r][j] = qq[r][j + 1];
-            qq[r][QQ - 1] = P.q1[r];
+            qa[r][PH + Q] = P.head[r];
+            qq[r][PH + QQ] = P.q1[r];
         }
         const bool n1 = (unsigned)c1 < (unsigned)a.nx, n2 = (unsigned)c2 < (unsigned)a.nx;
         float o1v[PY];
-        update<Q - 1 - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0,
+        update<PH + Q - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0,
                           tab<1, kIb>(P.tab), tab<1, kIe>(P.tab), o1v);
         if (n1) record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), o1v);
         {
@@ -428,22 +450,18 @@ struct WaveKernel {
             for (int r = 0; r < PY; ++r) bstore<kCoherent>(rw, th.bo[r], o1v[r]);
         }
 #pragma unroll
-        for (int r = 0; r < PY; ++r) {
-#pragma unroll
-            for (int j = 0; j + 1 < Q; ++j) qb[r][j] = qb[r][j + 1];
-            qb[r][Q - 1] = o1v[r];
-        }
+        for (int r = 0; r < PY; ++r) qb[r][PH + Q] = o1v[r];
 
-        // level 2 at c2: update from the level-1 queue (centre entry M); the
-        // level below it is u^n at c2, entry 0 of the u^n queue, and q at c2
-        // entry 0 of the q queue
+        // level 2 at c2: update from the level-1 window (centre entry M); the
+        // level below it is u^n at c2, entry 0 of the u^n window, and q at c2
+        // entry 0 of the q window
         float up[PY], q2[PY], o2v[PY];
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
-            up[r] = qa[r][0];
-            q2[r] = qq[r][0];
+            up[r] = qa[r][PH + 1];
+            q2[r] = qq[r][PH + 1];
         }
-        update<M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1,
+        update<PH + 1 + M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1,
                   tab<2, kIb>(P.tab), tab<2, kIe>(P.tab), o2v);
         if (n2) record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), o2v);
         const auto ro = plane_rsrc(a.o1, c2, a.sxy, n2);
