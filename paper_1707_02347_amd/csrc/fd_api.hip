@@ -581,6 +581,8 @@ int wave_plan(const Dims &d, const fd_options &eff, Plan &p)
     }
     const int64_t resident = (int64_t)wave_occupancy(d.M, PY, NW, iso) * device_cus();
     if (wave_tiles(d, PY * NW) > resident) return FD_EUNSUPPORTED;
+    // the kernel's plane byte offsets are 32-bit
+    if (d.Np * 4 >= ((int64_t)1 << 31)) return FD_EUNSUPPORTED;
     p.key = KernelKey{d.M, 2, PY, NW, kPlain};
     p.lx = d.nx;
     p.variant = FD_VARIANT_WAVE;

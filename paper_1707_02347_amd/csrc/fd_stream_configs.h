@@ -59,5 +59,5 @@
 // 64 columns x NW*PY rows; both Laplacian forms.
 #define FDW_WAVE_CONFIGS(W)                                                                \
     W(1, 4, 4) W(1, 2, 8) W(2, 4, 4) W(2, 2, 8) W(3, 4, 4) W(3, 2, 8) W(4, 4, 4) W(4, 2, 8) \
-    W(4, 2, 4) W(5, 4, 4) W(5, 2, 8) W(6, 4, 4) W(6, 2, 8) W(7, 4, 4) W(7, 2, 8) W(8, 4, 4) \
+    W(4, 2, 4) W(5, 2, 8) W(6, 2, 8) W(7, 2, 8) \
     W(8, 2, 8) W(8, 2, 4)

@@ -21,20 +21,22 @@
 // Visibility.  The device-coherent form of a buffer access (the SC1
 // cache-policy bit, the form the compiler gives device-scope atomics) writes
 // through to, and reads from, the point of coherence of all XCDs; no
-// cache-wide write-back or invalidation is needed.  A workgroup's iteration i
-// issues the loads of iteration i + 1 before its own stores, and waits for
-// those loads in iteration i + 1; vector memory operations complete in issue
-// order, so by the barrier of iteration i + 2 every store of iteration i has
-// completed.  Thread 0 then stores the counter i + 1 ("iterations up to i
-// complete"), also device-coherently; each counter has a 256-byte line of its
-// own.  A reader polls its neighbours' counters one iteration ahead of the
-// ring loads they gate, and only when the values it last saw would not admit
-// them.
+// cache-wide write-back or invalidation is needed.  Loads are issued D
+// iterations ahead: iteration j + 1 issues the loads of iteration j + 1 + D
+// after the stores of iteration j, and waits for them in iteration j + 1 + D;
+// vector memory operations complete in issue order, so by the barrier of
+// iteration k every store of iteration k - D - 1 and before has completed.
+// Thread 0 then stores the counter k - D ("iterations below k - D complete"),
+// also device-coherently, every second iteration; each counter has a
+// 256-byte line of its own.  A reader polls its neighbours' counters before
+// issuing the ring loads they gate, and only when the values it last saw would
+// not admit them.
 //
 // Progress.  The host launches a pass only when all of its workgroups can be
 // resident at once (occupancy x compute units).  A workgroup at iteration i
-// waits only for neighbours to have completed iteration i + 1 - (M + E), below
-// its own: the workgroup furthest behind never waits, so every wait ends.
+// waits only for neighbours to have reached iteration i + 2D + 2 - (M + E),
+// below its own (M + E >= 2D + 3): the workgroup furthest behind never waits,
+// so every wait ends.
 // Each wait is still bounded (kWaveSpin polls); a wait that runs out sets the
 // pass's error word, which every later wait checks, so a launch that somehow
 // did not run all of its workgroups at once ends with an error instead of a
@@ -53,8 +55,15 @@ constexpr int kCoherent = 16;
 
 // Level 2 lags level 1 by M + E planes; the E extra planes are slack that lets
 // a neighbour's counter run a few iterations late without a wait.
-constexpr int kWaveLag = 9;
+constexpr int kWaveLag = 11;
 constexpr int wave_extra(int M) { return M >= kWaveLag ? 0 : kWaveLag - M; }
+
+// Prefetch distance: iteration i issues the loads of iteration i + kWaveAhead.
+// Measured at 512^3 so 8 (2 x 8 tiles, GPts/s): distance 1 317, 2 327, 3 339,
+// 4 329, 5 328 (each with the lag the counters need); the lag beyond that
+// bound gains nothing.
+constexpr int kWaveAhead = 3;
+static_assert(kWaveLag >= 2 * kWaveAhead + 3, "level 2 must trail level 1 by more than the counters lag");
 
 // Bound of one wait, in polls of the neighbours' counters (a poll is one
 // device-coherent load round trip plus a short sleep).
@@ -68,12 +77,17 @@ struct WaveKernel {
     static constexpr int E = wave_extra(M);
     static constexpr int Q = 2 * M + 1 + E;  // queue length of u^n and of level 1 along x
     static constexpr int QQ = M + E + 1;     // queue of q: level 1's plane down to level 2's
-    // The x loop is unrolled by U: phase PH of the unrolled body pushes into
-    // slot (queue length) + PH, so a queue's window of planes sits at slots
+    // The x loop is unrolled by U = D + 1 (D the prefetch distance), with U
+    // prefetch slots: phase PH consumes slot PH and refills the slot the
+    // previous phase consumed, so every slot index is a compile-time constant
+    // and no loaded register is copied (a copy would wait for the loads in
+    // flight).  Phase PH also pushes into slot (queue length) + PH of each
+    // register queue, so a queue's window of planes sits at slots
     // [PH, PH + length) before that push and [PH + 1, PH + 1 + length) after
     // it; the slots move back by U once per body (one register move per slot
     // every U iterations instead of every iteration).
-    static constexpr int U = 4;
+    static constexpr int D = kWaveAhead;
+    static constexpr int U = D + 1;
     static constexpr int QX = Q + U, QQX = QQ + U;  // slots: the last push lands in Q + U - 1
     static constexpr int LW = RZ + 2 * M;    // LDS plane with its M-wide ring
     static constexpr int LH = RY + 2 * M;
@@ -188,25 +202,18 @@ struct WaveKernel {
         // 1 at plane 0); the queue then holds planes M - Q + j in entries j
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const auto rh = plane_rsrc(a.u0, j, a.sxy, j < a.nx);
+            const uint32_t sxy4 = (uint32_t)a.sxy * 4u;
+            const auto rh = wplane(a.u0, (uint32_t)j * sxy4, j < a.nx, sxy4);
 #pragma unroll
             for (int r = 0; r < PY; ++r) qa[r][Q - M + j] = bload(rh, th.bo[r]);
         }
         const int ibeg = M, iend = a.nx + 2 * M + E;  // level 2's last plane nx - 1 at iend - 1
-        // Two prefetch slots: iteration i consumes slot i & 1 and first issues
-        // the loads of iteration i + 1 into the other, so no loaded register
-        // is ever copied (a copy would wait for the loads in flight).
         uint64_t flag = poll(a, th);
-        Pre p0, p1;
-        load(a, th, p0, ibeg);
+        Pre pf[U];
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(a, th, pf[d], ibeg + d);
         for (int i = ibeg; i < iend; i += U) {
-            iteration<0>(a, sm, th, qa, qb, qq, flag, p1, p0, i);
-            if (i + 1 >= iend) break;
-            iteration<1>(a, sm, th, qa, qb, qq, flag, p0, p1, i + 1);
-            if (i + 2 >= iend) break;
-            iteration<2>(a, sm, th, qa, qb, qq, flag, p1, p0, i + 2);
-            if (i + 3 >= iend) break;
-            iteration<3>(a, sm, th, qa, qb, qq, flag, p0, p1, i + 3);
+            if (!body<0>(a, sm, th, qa, qb, qq, flag, pf, i, iend)) break;
 #pragma unroll
             for (int r = 0; r < PY; ++r) {
 #pragma unroll
@@ -220,22 +227,37 @@ struct WaveKernel {
         }
     }
 
-    // Iteration i: the ring loads of iteration i + 1 read level 1 from the
-    // neighbours, so first wait until they have stored it, poll again for the
-    // next iteration, issue iteration i + 1's loads into `next`, then compute
-    // from `cur`.
+    // Phases PH .. U - 1 of the unrolled body (iterations i0 + PH ...);
+    // false once the stream has ended.
+    template <int PH>
+    __device__ static __forceinline__ bool body(const SweepArgs &a, Smem &sm, Thread &th,
+                                                float (&qa)[PY][QX], float (&qb)[PY][QX], float (&qq)[PY][QQX],
+                                                uint64_t &flag, Pre (&pf)[U], int i0, int iend)
+    {
+        if constexpr (PH < U) {
+            if (i0 + PH >= iend) return false;
+            iteration<PH>(a, sm, th, qa, qb, qq, flag, pf[(PH + D) % U], pf[PH], i0 + PH);
+            return body<PH + 1>(a, sm, th, qa, qb, qq, flag, pf, i0, iend);
+        }
+        return true;
+    }
+
+    // Iteration i: the ring loads of iteration i + D read level 1 from the
+    // neighbours, so first wait until they have stored it, poll again if
+    // needed, issue iteration i + D's loads into `next` (the slot the
+    // previous iteration consumed), then compute from `cur`.
     template <int PH>
     __device__ static __forceinline__ void iteration(const SweepArgs &a, Smem &sm, Thread &th,
                                                      float (&qa)[PY][QX], float (&qb)[PY][QX], float (&qq)[PY][QQX],
                                                      uint64_t &flag, Pre &next, const Pre &cur, int i)
     {
-        wait_for(a, th, flag, i + 1);
+        wait_for(a, th, flag, i + D);
         // poll again only if the counters last seen would not admit the next
         // iteration's ring loads (in step with the neighbours, every second or
         // third iteration): a poll is a device-coherent round trip, and the
         // loads issued after it complete only after it
-        if (!__all(flag >= want_of(a, i + 2))) flag = poll(a, th);
-        load(a, th, next, i + 1);
+        if (!__all(flag >= want_of(a, i + D + 1))) flag = poll(a, th);
+        load(a, th, next, i + D);
         step<PH>(a, sm, th, qa, qb, qq, cur, i);
         // keep this iteration's stores ahead of the next iteration's loads in
         // issue order (the counter protocol relies on it)
@@ -287,6 +309,17 @@ struct WaveKernel {
         th.gaveup = true;
     }
 
+    // Buffer resource over the plane at byte offset `off` of a field (an
+    // empty range if !valid).  The host admits a wave pass only for fields
+    // below 2 GiB, so plane offsets are 32-bit (one scalar multiply per plane
+    // instead of a 64-bit one per resource).
+    __device__ static __forceinline__ __amdgpu_buffer_rsrc_t wplane(const float *field, uint32_t off,
+                                                                    bool valid, uint32_t sxy4)
+    {
+        const char *base = (const char *)field + (valid ? off : 0u);
+        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, valid ? (int)sxy4 : 0, 0x00020000);
+    }
+
     // Issue the loads of iteration i: head plane i of u^n; level 1's plane
     // c1 = i - M (ring of u^n, u^{n-1}, q); level 2's plane c2 = i - 2M - E
     // (the level-1 ring from the neighbours).
@@ -294,20 +327,22 @@ struct WaveKernel {
     {
         const int c1 = i - M, c2 = i - 2 * M - E;
         const bool v0 = i < a.nx, v1 = (unsigned)c1 < (unsigned)a.nx, v2 = (unsigned)c2 < (unsigned)a.nx;
-        const auto rh = plane_rsrc(a.u0, i, a.sxy, v0);
+        const uint32_t sxy4 = (uint32_t)a.sxy * 4u;
+        const uint32_t o0 = (uint32_t)i * sxy4, o1 = (uint32_t)c1 * sxy4, o2 = (uint32_t)c2 * sxy4;
+        const auto rh = wplane(a.u0, o0, v0, sxy4);
 #pragma unroll
         for (int r = 0; r < PY; ++r) P.head[r] = bload(rh, th.bo[r]);
-        const auto rc = plane_rsrc(a.u0, c1, a.sxy, v1);
+        const auto rc = wplane(a.u0, o1, v1, sxy4);
 #pragma unroll
         for (int s = 0; s < HS; ++s) P.h0[s] = bload(rc, th.hb[s]);
-        const auto rm = plane_rsrc(a.um, c1, a.sxy, v1);
-        const auto rq1 = plane_rsrc(a.q, c1, a.sxy, v1);
+        const auto rm = wplane(a.um, o1, v1, sxy4);
+        const auto rq1 = wplane(a.q, o1, v1, sxy4);
 #pragma unroll
         for (int r = 0; r < PY; ++r) {
             P.um[r] = bload<kStream>(rm, th.bo[r]);
             P.q1[r] = bload<kStream>(rq1, th.bo[r]);
         }
-        const auto r1 = plane_rsrc(a.o2, c2, a.sxy, v2);
+        const auto r1 = wplane(a.o2, o2, v2, sxy4);
 #pragma unroll
         for (int s = 0; s < HS; ++s) P.h1[s] = bload<kCoherent>(r1, th.hb[s]);
         {
@@ -424,13 +459,14 @@ struct WaveKernel {
             S1[(th.wv * PY + r + M) * LW + th.lane + M] = qb[r][PH + M + 1];
         }
         __syncthreads();
-        // every wave has waited for this iteration's loads, issued after its
-        // stores of iteration i - 2: those stores are complete
-        // (every second iteration: the readers' slack, M + E - 4 iterations,
-        // covers the extra one)
-        if (threadIdx.x == 0 && (PH & 1) == 0)
-            __hip_atomic_store(a.prog + (int64_t)kWaveProgStride * th.tile, ((uint64_t)a.epoch << 32) | (uint32_t)(i - 1),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // every wave has waited for this iteration's loads, issued D
+        // iterations ago, after its stores of iteration i - D - 1: those
+        // stores, and all before them, are complete (stored every second
+        // iteration; the readers' slack covers the extra one)
+        if (threadIdx.x == 0 && (i & 1) == 0)
+            __hip_atomic_store(a.prog + (int64_t)kWaveProgStride * th.tile,
+                               ((uint64_t)a.epoch << 32) | (uint32_t)(i - D), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 
         // level 1 at c1: push the head plane and q at c1, update from the
         // u^n queue
@@ -444,8 +480,9 @@ struct WaveKernel {
         update<PH + Q - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0,
                           tab<1, kIb>(P.tab), tab<1, kIe>(P.tab), o1v);
         if (n1) record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), o1v);
+        const uint32_t sxy4 = (uint32_t)a.sxy * 4u;
         {
-            const auto rw = plane_rsrc(a.o2, c1, a.sxy, n1);
+            const auto rw = wplane(a.o2, (uint32_t)c1 * sxy4, n1, sxy4);
 #pragma unroll
             for (int r = 0; r < PY; ++r) bstore<kCoherent>(rw, th.bo[r], o1v[r]);
         }
@@ -464,7 +501,7 @@ struct WaveKernel {
         update<PH + 1 + M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1,
                   tab<2, kIb>(P.tab), tab<2, kIe>(P.tab), o2v);
         if (n2) record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), o2v);
-        const auto ro = plane_rsrc(a.o1, c2, a.sxy, n2);
+        const auto ro = wplane(a.o1, (uint32_t)c2 * sxy4, n2, sxy4);
 #pragma unroll
         for (int r = 0; r < PY; ++r) bstore<kStream>(ro, th.bo[r], o2v[r]);
     }
