@@ -18,6 +18,7 @@ extern "C" {
 void *hc_dev_alloc(size_t bytes);
 void hc_dev_free(void *p);
 int hc_errors(void);
+void hc_force_wave_timeout(int on);
 int hc_warnings(void);
 void hc_stats(long *launches, long *checked, long *grouped, long *graphs);
 int hc_live_handles(void);
@@ -393,6 +394,22 @@ int main()
         }
         std::printf("random draws: %d ran, %d not compiled\n", ok, unsupported);
         expect(ok >= 60 ? FD_OK : -100, FD_OK, "random draws mostly compiled");
+    }
+    // a pass without redundant halos whose wait ran out (forced by the
+    // stand-in): the call reports FD_ESYNC; the next call on the same
+    // workspace clears the error word before its first such pass
+    {
+        const fd_time t{21, stable_dt(g3)};
+        const fd_options o = opts(FD_VARIANT_WAVE);
+        const size_t ws = fd_workspace_size(&g3, &t, nullptr, nullptr, &o, FD_OP_FORWARD);
+        Buf w(ws), v(points(g3) * 4), st(2 * points(g3) * 4);
+        for (int64_t i = 0; i < points(g3); ++i) v.f()[i] = 2000.0f;
+        hc_force_wave_timeout(1);
+        expect(fd_forward(&g3, &t, v.f(), nullptr, nullptr, nullptr, st.f(), w.p, ws, &o, nullptr), FD_ESYNC,
+               "wave pass whose wait ran out");
+        hc_force_wave_timeout(0);
+        expect(fd_forward(&g3, &t, v.f(), nullptr, nullptr, nullptr, st.f(), w.p, ws, &o, nullptr), FD_OK,
+               "the next call clears the error word");
     }
     // adjoint, gradients (checkpointed and whole time axis), vjp, Born
     adjoint_case("so8", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM));

@@ -35,6 +35,7 @@
 namespace {
 
 int g_errors = 0;
+bool g_force_wave_timeout = false;  // wave passes end as if a wait ran out
 int g_warnings = 0;
 long g_launches = 0, g_checked = 0, g_grouped = 0, g_graph_launches = 0;
 
@@ -152,7 +153,7 @@ struct KInfo {
     std::string name;  // demangled
     int tmpl[8] = {};
     int ntmpl = 0;
-    enum { kOther, kStream, kGrouped, kWave } kind = kOther;
+    enum { kOther, kStream, kGrouped, kWave, kZero } kind = kOther;
 };
 // registered from the objects' module constructors, which may run before this
 // file's globals are constructed: built on first use
@@ -440,6 +441,7 @@ void __hipRegisterFunction(void **, const void *host, char *, const char *dev_na
     if (k.name.rfind("void fdw::k_stream_grouped<", 0) == 0) k.kind = KInfo::kGrouped;
     else if (k.name.rfind("void fdw::k_stream<", 0) == 0) k.kind = KInfo::kStream;
     else if (k.name.rfind("void fdw::k_wave<", 0) == 0) k.kind = KInfo::kWave;
+    else if (k.name.rfind("fdw::k_zero(", 0) == 0) k.kind = KInfo::kZero;
     parse_template(k);
     kernels()[host] = k;
 }
@@ -497,9 +499,23 @@ hipError_t hipLaunchKernel(const void *fn, dim3 grid, dim3 block, void **args, s
     // the arguments are only valid during the call: copy what the checks read
     if (k.kind == KInfo::kStream || k.kind == KInfo::kWave) {
         SweepArgs a = *reinterpret_cast<const SweepArgs *>(args[0]);
-        enqueue(S(s, "hipLaunchKernel"), [k, grid, block, a]() {
+        const bool timeout = k.kind == KInfo::kWave && g_force_wave_timeout;
+        enqueue(S(s, "hipLaunchKernel"), [k, grid, block, a, timeout]() {
             void *ar[1] = {(void *)&a};
             check_launch(k, grid, block, ar);
+            if (timeout && in_dev(a.err, 4)) *a.err = 1;  // what a wait that runs out leaves
+        });
+    } else if (k.kind == KInfo::kZero) {
+        // the fill kernel runs for real: the library clears counters and error
+        // words with it
+        uint32_t *p = *reinterpret_cast<uint32_t *const *>(args[0]);
+        const int64_t n = *reinterpret_cast<const int64_t *>(args[1]);
+        enqueue(S(s, "hipLaunchKernel"), [p, n]() {
+            if (n < 0 || !in_dev(p, (size_t)n * 4)) {
+                fail("k_zero over %lld words at %p outside the device buffers", (long long)n, (void *)p);
+                return;
+            }
+            std::memset(p, 0, (size_t)n * 4);
         });
     } else if (k.kind == KInfo::kGrouped) {
         const GroupEntry *list = *reinterpret_cast<const GroupEntry *const *>(args[0]);
@@ -762,6 +778,7 @@ void hc_dev_free(void *p)
     std::free(p);
 }
 int hc_errors(void) { return g_errors; }
+void hc_force_wave_timeout(int on) { g_force_wave_timeout = on != 0; }
 int hc_warnings(void) { return g_warnings; }
 void hc_stats(long *launches, long *checked, long *grouped, long *graphs)
 {

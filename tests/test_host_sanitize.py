@@ -5,14 +5,17 @@ and a driver that calls every entry point (tests/hostcheck/driver.cpp):
 forward sweeps of every variant, points on and between nodes (staged, routed
 and heavy tables), adjoint, checkpointed and whole-axis gradients, Born
 modelling, the autotuner, forward and gradient batches with and without graph
-capture, and error paths.
+capture, and error paths (among them a two-level exchange pass whose wait ran
+out, which the stand-in forces by setting the pass's error word: the call must
+return FD_ESYNC, and the next call on the same workspace must clear it).
 
 Besides the sanitizers' own checks, the stand-in checks every sweep kernel's
 arguments (single-pass and every entry of a grouped launch's table) against
 the buffers the caller passed, the tile counts against the grid, the rows each
-time level injects or records, the capacity of staged point walks, stream and
-event lifetimes, and graph capture's fork/join rules; a batch must release
-every event and graph it creates."""
+time level injects or records, the capacity of staged point walks, exchange
+passes' residency, counter capacity and epochs, every fill kernel's range
+(fills run for real), stream and event lifetimes, and graph capture's
+fork/join rules; a batch must release every event and graph it creates."""
 import os
 import subprocess
 
