@@ -418,6 +418,8 @@ int main()
                  opts(FD_VARIANT_TBLOCK, 0, 0, 0, 2));
     gradient_case("so8 ckpt 7", g3, 30, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_STREAM, 0, 0, 0, 0, 0, 7),
                   false);
+    gradient_case("so8 wave ckpt 7", g3, 30, centre_src(g3, 12), rec_line(g3, 7, 12),
+                  opts(FD_VARIANT_WAVE, 0, 0, 0, 0, 0, 7), false);
     gradient_case("so8 full", g3, 30, centre_src(g3, 12), rec_line(g3, 7, 12),
                   opts(FD_VARIANT_STREAM, 0, 0, 0, 0, 0, 30), false);
     gradient_case("so4 T2 ckpt 11", g4, 33, centre_src(g4, 15), rec_line(g4, 7, 15),

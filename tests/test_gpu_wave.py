@@ -85,6 +85,22 @@ def test_wave_adjoint_equals_untiled():
     assert torch.equal(out["src"], base["src"]) and torch.equal(out["lam"], base["lam"])
 
 
+def test_wave_gradient_equals_space_tiled():
+    """A gradient under an exchange plan: its checkpointing forward segments run
+    exchange passes, the recomputation and imaging passes the other kernels;
+    the checkpoints, hence the gradient, are the same bits as under the
+    space-tiled plan."""
+    cs = make_case((40, 52, 90), 8, 33, 5, nrec=12)
+    v = cs["v"].to(DEV)
+    amp = torch.from_numpy(cs["amp"]).to(DEV)
+    d_obs = 1e-3 * torch.from_numpy(np.random.default_rng(3).standard_normal((cs["nt"], len(cs["rec"]))).astype(np.float32)).to(DEV)
+    args = (v, cs["h"], cs["so"], cs["nt"], cs["dt"], cs["src"], amp, cs["rec"], d_obs)
+    ja, ga, ra = api.gradient(*args, sponge=cs["sponge"], vref=cs["vref"], variant=L.FD_VARIANT_WAVE, ckpt_every=7)
+    jb, gb, rb = api.gradient(*args, sponge=cs["sponge"], vref=cs["vref"], variant=L.FD_VARIANT_STREAM, ckpt_every=7)
+    assert float(gb.abs().max()) > 0
+    assert ja == jb and torch.equal(ga, gb) and torch.equal(ra, rb)
+
+
 def test_wave_plan_needs_every_tile_resident():
     """A grid with more tiles than the device holds at once is refused."""
     v = torch.full((8, 2048, 4096), 2000.0, device=DEV)  # 64 x 128 tiles of 64 x 16
