@@ -127,8 +127,10 @@ extern "C" {
                                 exchange through the pass's u^{n+1} field).  tile[0] is
                                 ignored (the whole axis), tile[1] / tile[2] choose the
                                 tile's rows and rows per thread; tblock must be 0 or 2.
-                                All of a pass's workgroups must fit on the device at once
-                                (FD_EUNSUPPORTED otherwise); the call waits for its
+                                All of a pass's workgroups must fit on the device at once,
+                                and each field must be below 2 GiB (FD_EUNSUPPORTED
+                                otherwise; an automatic plan whose cached choice is this
+                                variant falls back to the default then); the call waits for its
                                 passes to finish and returns FD_ESYNC if a wait ran out.
                                 Plain forward and adjoint passes only: gradient and Born
                                 passes, passes whose point tables are injected or recorded

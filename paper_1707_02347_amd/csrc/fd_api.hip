@@ -599,6 +599,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
                                 FD_FLAG_NO_X_ALTERNATE | FD_FLAG_LOADS_STREAM | FD_FLAG_LOADS_KEEP))
         return FD_EINVAL;
     if ((eff.flags & FD_FLAG_LOADS_STREAM) && (eff.flags & FD_FLAG_LOADS_KEEP)) return FD_EINVAL;
+    const bool automatic = eff.variant == FD_VARIANT_AUTO;
     if (eff.variant == FD_VARIANT_AUTO) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file();
@@ -632,7 +633,22 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
         p.lx = d.nx;
         return FD_OK;
     }
-    if (eff.variant == FD_VARIANT_WAVE) return wave_plan(d, eff, p);
+    if (eff.variant == FD_VARIANT_WAVE) {
+        const int rc = wave_plan(d, eff, p);
+        // a cached choice this device cannot run (fewer compute units than the
+        // one it was tuned on) falls back to the default plan
+        if (rc != FD_EUNSUPPORTED || !automatic) return rc;
+        eff = fd_options{};
+        if (o) eff.flags = o->flags;
+        eff.variant = (d.ndim == 3) ? FD_VARIANT_STREAM : FD_VARIANT_NAIVE;
+        p.variant = eff.variant;
+        p.wave = false;
+        if (eff.variant == FD_VARIANT_NAIVE) {
+            p.key = KernelKey{d.M, 1, 1, 1, kPlain};
+            p.lx = d.nx;
+            return FD_OK;
+        }
+    }
     if (eff.variant != FD_VARIANT_STREAM && eff.variant != FD_VARIANT_TBLOCK && eff.variant != FD_VARIANT_SPLIT)
         return FD_EINVAL;
     int T = 1;

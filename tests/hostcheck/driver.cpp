@@ -288,6 +288,15 @@ void batch_case(const std::string &name, const std::vector<ShotSpec> &specs, boo
 
 int main()
 {
+    // a cached exchange choice for a grid of 576 tiles, more than the stand-in's
+    // 512 resident workgroups: written before the library first reads its cache
+    const fd_grid gbig = grid({3, 136, 4096}, 8, 0);
+    if (const char *cache = std::getenv("FD_AUTOTUNE_CACHE")) {
+        if (FILE *f = std::fopen(cache, "a")) {
+            std::fprintf(f, "3 3 136 4096 8 gfx950 iso %d 3 16 2 2\n", FD_VARIANT_WAVE);
+            std::fclose(f);
+        }
+    }
     const fd_grid g3 = grid({40, 38, 44}, 8), g3p = grid({36, 40, 64}, 8);
     // forward: every variant, state in and out (converted and in place), cache policies
     forward_case("so8 naive", g3, 24, centre_src(g3, 12), rec_line(g3, 7, 12), opts(FD_VARIANT_NAIVE), true);
@@ -394,6 +403,23 @@ int main()
         }
         std::printf("random draws: %d ran, %d not compiled\n", ok, unsupported);
         expect(ok >= 60 ? FD_OK : -100, FD_OK, "random draws mostly compiled");
+    }
+    // an automatic plan whose cached exchange choice cannot be resident on this
+    // device falls back to the default plan
+    if (std::getenv("FD_AUTOTUNE_CACHE")) {
+        const fd_time t{4, stable_dt(gbig)};
+        const fd_options o = opts();
+        const size_t ws = fd_workspace_size(&gbig, &t, nullptr, nullptr, &o, FD_OP_FORWARD);
+        Buf w(ws), v(points(gbig) * 4), st(2 * points(gbig) * 4);
+        for (int64_t i = 0; i < points(gbig); ++i) v.f()[i] = 2000.0f;
+        expect(fd_forward(&gbig, &t, v.f(), nullptr, nullptr, nullptr, st.f(), w.p, ws, &o, nullptr), FD_OK,
+               "automatic plan with an exchange choice that cannot be resident");
+        fd_options last{};
+        fd_last_config(&last);
+        expect(last.variant == FD_VARIANT_STREAM ? FD_OK : -100, FD_OK, "it ran the space-tiled default");
+        fd_options wv = opts(FD_VARIANT_WAVE);
+        expect(fd_forward(&gbig, &t, v.f(), nullptr, nullptr, nullptr, st.f(), w.p, ws, &wv, nullptr),
+               FD_EUNSUPPORTED, "an explicit exchange plan that cannot be resident");
     }
     // a pass without redundant halos whose wait ran out (forced by the
     // stand-in): the call reports FD_ESYNC; the next call on the same
