@@ -134,3 +134,24 @@ def test_wave_full_size_equals_untiled(so):
     assert float(outs[0].abs().max()) > 0
     for o in outs[1:]:
         assert torch.equal(outs[0], o)
+
+
+@pytest.mark.parametrize("so,tile", [(8, (0, 16, 2)), (8, (0, 8, 2)), (4, (0, 16, 2))])
+def test_wave_long_sweep_equals_space_tiled(so, tile):
+    """1000 steps at 512^3 (500 exchange passes, each with every workgroup
+    publishing and polling counters some 500 times): any read of a neighbour's
+    level 1 before it was stored would change bits somewhere in the field."""
+    import bench
+
+    print(f"wave 512^3 so {so} tile {tile}, 1000 steps", flush=True)
+    cs = bench.workload("cfg3", device=DEV)
+    nt = 1000
+    dt = 0.8 * bench.courant_max(so, 3) * 10.0 / 4500.0
+    amp = torch.from_numpy(synth.ricker(nt, dt, 15.0)[:, None].copy()).to(DEV)
+    a = api.forward(cs["v"], cs["h"], so, nt, dt, cs["src"], amp, None, sponge=cs["sponge"], vref=cs["vref"],
+                    variant=L.FD_VARIANT_WAVE, tile=tile)
+    assert api.last_config()["variant"] == L.FD_VARIANT_WAVE
+    b = api.forward(cs["v"], cs["h"], so, nt, dt, cs["src"], amp, None, sponge=cs["sponge"], vref=cs["vref"],
+                    variant=L.FD_VARIANT_STREAM)
+    assert float(b["u"].abs().max()) > 0
+    assert torch.equal(a["u"], b["u"]) and torch.equal(a["u_prev"], b["u_prev"])
