@@ -251,9 +251,13 @@ def roofline_of(sweep_ms, setup, launches, npts, bytes_per_point, kernel, profil
     kern_ms = max(sweep_ms - setup, 1e-6) / launches
     bpl = bytes_per_point * npts
     achieved = bpl / (kern_ms * 1e-3) / 1e9
+    traffic = profiled_traffic(profile, kernel) if profile else None
+    # traffic: counted HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, copy
+    # calibrated), beside the algorithmic bytes per launch
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": profiled_traffic(profile, kernel) if profile else None,
+            "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / bpl, 3) if traffic else None,
             "kernel": kernel, "avg_launch_us": round(kern_ms * 1e3, 2), "launches": launches,
             "bytes_per_launch": bpl, "bytes_per_point": bytes_per_point}
 
