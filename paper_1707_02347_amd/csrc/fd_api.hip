@@ -350,6 +350,7 @@ struct Layout {
     uint64_t *prog = nullptr;       // progress counters of passes without redundant halos
     int *err = nullptr;             // their error word
     int nprog = 0;
+    int32_t *ptab = nullptr;        // their per-plane table ([nx][kPlaneTab])
     // gradient
     float *ckpt = nullptr;          // [nck][2][N]
     int nck = 0;
@@ -400,6 +401,7 @@ Layout layout(void *ws, const Dims &d, int64_t nt, const PtsSpec &S, const PtsSp
     L.nprog = ((d.nz + 63) / 64) * ((d.ny + 7) / 8);
     L.prog = cv.take<uint64_t>((size_t)L.nprog * kWaveProgStride);
     L.err = cv.take<int>(64);
+    L.ptab = cv.take<int32_t>((size_t)d.nx * kPlaneTab);
     if (op == FD_OP_BORN) L.seg = cv.take<float>(d.Np);  // the background's second difference
     if (op == FD_OP_GRADIENT || op == FD_OP_VJP) {
         L.nck = nt > 0 ? (int)((nt + K - 1) / K) : 0;
@@ -939,6 +941,26 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
     FDW_HIP(hipStreamSynchronize(s));
 }
 
+// The per-plane table of passes without redundant halos: per x-plane the
+// sponge profile, the source and receiver entry ranges, and whether they are
+// non-empty (one vector load per iteration reads it, lane k holding slot k).
+void upload_planes(const Dims &d, const float *px, const std::vector<int32_t> &xs,
+                   const std::vector<int32_t> &xr, int32_t *dst, hipStream_t s)
+{
+    std::vector<int32_t> t((size_t)d.nx * kPlaneTab, 0);
+    for (int c = 0; c < d.nx; ++c) {
+        int32_t *e = &t[(size_t)c * kPlaneTab];
+        std::memcpy(&e[0], &px[c], 4);
+        e[1] = xs.size() > (size_t)c + 1 ? xs[c] : 0;
+        e[2] = xs.size() > (size_t)c + 1 ? xs[c + 1] : 0;
+        e[3] = xr.size() > (size_t)c + 1 ? xr[c] : 0;
+        e[4] = xr.size() > (size_t)c + 1 ? xr[c + 1] : 0;
+        e[5] = (e[2] > e[1] ? 1 : 0) | (e[4] > e[3] ? 2 : 0);
+    }
+    FDW_HIP(hipMemcpyAsync(dst, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
+    FDW_HIP(hipStreamSynchronize(s));
+}
+
 PointTable as_table(const TableBufs &b, int stride, int cnt, bool with_scale)
 {
     PointTable t;
@@ -1154,6 +1176,7 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     if (rc) return rc;
     upload_table(d, es, c.L.src, inj ? inj->n : 0, &c.hxs, c.s);
     upload_table(d, er, c.L.rec, rec ? rec->n : 0, &c.hxr, c.s);
+    upload_planes(d, prof.data(), c.hxs, c.hxr, c.L.ptab, c.s);
 
     SweepArgs &a = c.base;
     std::memset(&a, 0, sizeof a);
@@ -1172,6 +1195,7 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     a.rscale = 1.0f;
     a.adir = 1;
     a.rdir = 1;
+    a.ptab = c.L.ptab;
     FDW_HIP(launch_entry_x(a.inj, d.nx, c.L.src.xe, c.s));
     FDW_HIP(launch_entry_x(a.rec, d.nx, c.L.rec.xe, c.s));
     FDW_HIP(launch_scales(a, a.inj, c.L.src.scale, inj_alpha, c.s));
@@ -1284,7 +1308,8 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // two levels without redundant halos: plain passes with both steps
         // left, issued immediately, whose point tables need no separate route
         // (such tables and single-step tails take the passes below)
-        if (c.plan.wave && !c.ex.rec && so.mode == kPlain && !isep && !rsep && nsteps - s >= 2) {
+        if (c.plan.wave && !c.ex.rec && so.mode == kPlain && !isep && !rsep && nsteps - s >= 2 &&
+            a.inj.xptr == c.L.src.xptr && a.rec.xptr == c.L.rec.xptr && a.ptab == c.L.ptab) {
             const KernelKey &k = c.plan.key;
             a.u0 = st.cur;
             a.um = st.prev;
@@ -2279,6 +2304,7 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         std::vector<Entry> none;
         upload_table(d, none, c.L.src, 0, &c.hxs, s);
         upload_table(d, none, c.L.rec, 0, &c.hxr, s);
+        upload_planes(d, prof.data(), c.hxs, c.hxr, c.L.ptab, s);
         SweepArgs &a = c.base;
         std::memset(&a, 0, sizeof a);
         a.nx = d.nx;
@@ -2295,6 +2321,7 @@ extern "C" int fd_autotune(const fd_grid *grid, const fd_time *time, fd_options 
         a.rec = as_table(c.L.rec, 0, 0, false);
         a.rscale = 1.0f;
         a.adir = a.rdir = 1;
+        a.ptab = c.L.ptab;
         struct Events {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             ~Events()

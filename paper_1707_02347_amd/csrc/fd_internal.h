@@ -115,7 +115,12 @@ struct SweepArgs {
     uint64_t *prog;
     int *err;
     uint32_t epoch;
+    // Per-plane scalars of those passes, [nx][8]: the sponge profile px (as
+    // bits), the plane's source entry range [ib, ie), its receiver entry range
+    // [rb, re), and flags (bit 0: sources, bit 1: receivers on the plane).
+    const int32_t *ptab;
 };
+constexpr int kPlaneTab = 8;  // int32 slots per plane of SweepArgs::ptab
 
 // Point entries x time levels a workgroup can stage in LDS, the configurations
 // that can (the others would spill registers), and the table size below which

@@ -100,9 +100,10 @@ struct WaveKernel {
         float s1[2][LH * LW];  // level 1 at level 2's plane, with its ring
     };
 
-    // Loads of one iteration, issued one iteration ahead.  The per-plane
-    // scalars of both levels (sponge profile, point table ranges) are one
-    // vector load, lane k holding scalar k (read back with readlane): a
+    // Loads of one iteration, issued D iterations ahead.  The per-plane
+    // scalars of both levels (SweepArgs::ptab: sponge profile, point table
+    // ranges, flags) are one vector load, lane k holding slot k of level 1's
+    // plane and lane kTab + k that of level 2's (read back with readlane): a
     // scalar load would be waited for by the barrier's LDS wait (one counter
     // covers both), exposing its latency every iteration.
     struct Pre {
@@ -111,9 +112,9 @@ struct WaveKernel {
         float um[PY];         // u^{n-1} at level 1's plane
         float q1[PY];         // q at level 1's plane (level 2 takes it M + E iterations later)
         float h1[HS];         // level-1 ring at level 2's plane (the neighbours' values)
-        int tab;              // lanes 0-4: level 1's plane, 5-9: level 2's (kPx, kIb, kIe, kRb, kRe)
+        int tab;              // lanes 0-5: level 1's plane, 6-11: level 2's (kPx .. kFl)
     };
-    enum { kPx = 0, kIb = 1, kIe = 2, kRb = 3, kRe = 4, kTab = 5 };
+    enum { kPx = 0, kIb = 1, kIe = 2, kRb = 3, kRe = 4, kFl = 5, kTab = 6 };
 
     struct Thread {
         int lane, wv, tile, nbt;  // nbt: the neighbour tile lane 0..3 polls (-1: none)
@@ -346,15 +347,14 @@ struct WaveKernel {
 #pragma unroll
         for (int s = 0; s < HS; ++s) P.h1[s] = bload<kCoherent>(r1, th.hb[s]);
         {
-            // lane k < 10: scalar k % 5 of plane c1 (k < 5) or c2
+            // lane k < 2 kTab: slot k % kTab of plane c1 (k < kTab) or c2;
+            // other lanes and planes outside the grid read 0
             const int l = th.lane, k = l < kTab ? l : l - kTab;
             const int c = l < kTab ? c1 : c2;
-            const bool v = l < 2 * kTab && (unsigned)c < (unsigned)a.nx &&
-                           (k == kPx || (k <= kIe ? a.inj.cnt > 0 : a.rec.cnt > 0));
-            const int32_t *src = k == kPx ? (const int32_t *)a.px + c
-                                 : k <= kIe ? a.inj.xptr + c + (k - kIb)
-                                            : a.rec.xptr + c + (k - kRb);
-            P.tab = v ? *src : 0;
+            const bool v = l < 2 * kTab && (unsigned)c < (unsigned)a.nx;
+            const auto rt = span_rsrc(a.ptab, (int64_t)a.nx * kPlaneTab * 4, true);
+            P.tab = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rt, v ? (uint32_t)(c * kPlaneTab + k) * 4u : kOutside, 0, 0);
         }
     }
 
@@ -477,9 +477,16 @@ struct WaveKernel {
         }
         const bool n1 = (unsigned)c1 < (unsigned)a.nx, n2 = (unsigned)c2 < (unsigned)a.nx;
         float o1v[PY];
-        update<PH + Q - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0,
-                          tab<1, kIb>(P.tab), tab<1, kIe>(P.tab), o1v);
-        if (n1) record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), o1v);
+        // the entry ranges are read back only for planes that hold points
+        const int f1 = tab<1, kFl>(P.tab), f2 = tab<2, kFl>(P.tab);
+        int ib = 0, ie = 0;
+        if (f1 & 1) {
+            ib = tab<1, kIb>(P.tab);
+            ie = tab<1, kIe>(P.tab);
+        }
+        update<PH + Q - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0, ib,
+                          ie, o1v);
+        if (n1 && (f1 & 2)) record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), o1v);
         const uint32_t sxy4 = (uint32_t)a.sxy * 4u;
         {
             const auto rw = wplane(a.o2, (uint32_t)c1 * sxy4, n1, sxy4);
@@ -498,9 +505,14 @@ struct WaveKernel {
             up[r] = qa[r][PH + 1];
             q2[r] = qq[r][PH + 1];
         }
-        update<PH + 1 + M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1,
-                  tab<2, kIb>(P.tab), tab<2, kIe>(P.tab), o2v);
-        if (n2) record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), o2v);
+        ib = ie = 0;
+        if (f2 & 1) {
+            ib = tab<2, kIb>(P.tab);
+            ie = tab<2, kIe>(P.tab);
+        }
+        update<PH + 1 + M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1, ib, ie,
+                           o2v);
+        if (n2 && (f2 & 2)) record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), o2v);
         const auto ro = wplane(a.o1, (uint32_t)c2 * sxy4, n2, sxy4);
 #pragma unroll
         for (int r = 0; r < PY; ++r) bstore<kStream>(ro, th.bo[r], o2v[r]);

@@ -350,6 +350,18 @@ void check_wave(const Ctx &c, const KInfo &k, dim3 grid, dim3 block, const Sweep
           "sponge profiles outside the buffers");
     CHECK(in_dev(a.prog, (size_t)a.ntz * a.nty * fdw::kWaveProgStride * 8) && in_dev(a.err, 4),
           "counters outside the workspace");
+    CHECK(in_dev(a.ptab, (size_t)a.nx * fdw::kPlaneTab * 4), "per-plane table outside the workspace");
+    // the table must describe the pass's point tables
+    for (int x = 0; x < a.nx; ++x) {
+        const int32_t *e = a.ptab + (size_t)x * fdw::kPlaneTab;
+        const int ib = a.inj.cnt ? a.inj.xptr[x] : 0, ie = a.inj.cnt ? a.inj.xptr[x + 1] : 0;
+        const int rb = a.rec.cnt ? a.rec.xptr[x] : 0, re = a.rec.cnt ? a.rec.xptr[x + 1] : 0;
+        float px;
+        std::memcpy(&px, &e[0], 4);
+        CHECK(px == a.px[x] && e[1] == ib && e[2] == ie && e[3] == rb && e[4] == re &&
+                  e[5] == ((ie > ib ? 1 : 0) | (re > rb ? 2 : 0)),
+              "per-plane table entry %d does not match the pass's tables", x);
+    }
     CHECK(a.epoch >= 1, "epoch 0");
     uint32_t &last = epochs()[a.prog];
     CHECK(a.epoch == 1 || a.epoch == last + 1, "epoch %u after %u", a.epoch, last);
