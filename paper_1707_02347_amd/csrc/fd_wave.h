@@ -462,8 +462,11 @@ struct WaveKernel {
         // every wave has waited for this iteration's loads, issued D
         // iterations ago, after its stores of iteration i - D - 1: those
         // stores, and all before them, are complete (stored every second
-        // iteration; the readers' slack covers the extra one)
-        if (threadIdx.x == 0 && (i & 1) == 0)
+        // iteration; the readers' slack covers the extra one).  Nothing is
+        // stored while i - D < 1: a negative count would read as a huge one
+        // in the counter's low word, i.e. as every plane of the pass stored
+        // (the first iteration is i = M, below D for M < D).
+        if (threadIdx.x == 0 && (i & 1) == 0 && i > D)
             __hip_atomic_store(a.prog + (int64_t)kWaveProgStride * th.tile,
                                ((uint64_t)a.epoch << 32) | (uint32_t)(i - D), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
