@@ -562,8 +562,9 @@ int wave_plan(const Dims &d, const fd_options &eff, Plan &p)
 {
     if (eff.tblock != 0 && eff.tblock != 2) return FD_EINVAL;
     const bool iso = grid_iso(d);
-    // measured at 512^3 (so 8 / so 16): 2 x 8 302 / 246 GPts/s, 2 x 4 296 / -,
-    // 4 x 4 239 / 156 (1 x 16, dropped: 279 / 233)
+    // preference order from 512^3 sweeps: so 8 2 x 8 350 GPts/s, 2 x 4 336;
+    // 4 x 4 ran 20-35 % behind 2 x 8 (so 8 / so 16) in an earlier build, and
+    // 1 x 16 (no longer compiled) 8 % behind
     static const int shapes[][2] = {{2, 8}, {2, 4}, {4, 4}};
     int PY = 0, NW = 0;
     if (eff.tile[1] > 0 || eff.tile[2] > 0) {
