@@ -145,7 +145,7 @@ extern "C" {
 /* Cache policy of the loads each point makes once per step (u^{n-1}, the
  * coefficient field q, and the gradient's fields).  By default they are
  * non-temporal in single-step passes when the fields a step re-reads (u^n,
- * u^{n-1}, q; the FP64 image of a gradient) exceed 320 MiB, the share the
+ * u^{n-1}, q; the image's partial sums in a gradient) exceed 320 MiB, the share the
  * GPU's last-level cache keeps, and ordinary otherwise (time-blocked passes
  * share those loads between overlapping tiles); for a grouped batch launch
  * the fields of all its shots count.  The two flags force one policy (for A/B timing); setting
@@ -287,7 +287,9 @@ int fd_adjoint(const fd_grid *grid, const fd_time *time, const float *v,
  * Sec. 6.3.2, traded through recomputation).  With ckpt_every >= nt the whole
  * time axis is stored instead (workspace about nt fields): the forward sweep
  * saves every second difference and no recomputation runs, two sweeps instead
- * of three; results are identical.  The imaging sum is accumulated in FP64.
+ * of three; results are identical.  The imaging sum is carried in FP32 over
+ * blocks of 64 consecutive time steps (the same blocks for every checkpoint
+ * interval) and accumulated in FP64 across the blocks.
  *   src->amp DEVICE [nt][ns] source wavelet; rec->amp DEVICE [nt][nr] observed data.
  *   grad_v   DEVICE [N] FP32 result.
  *   misfit   HOST double or NULL (non-NULL: the call waits for it).

@@ -49,11 +49,12 @@ bool launch_stream_grouped(const KernelKey &k, bool iso, bool ntl, bool ps,
     return e && e->launch_group(iso, ntl, ps, list, nlist, total, grid, s);
 }
 
-// Bytes a pass re-reads every step: u^n, u^{n-1} and q, plus the FP64 image in
-// imaging mode (d2 snapshots and the new field are touched once).
+// Bytes a pass re-reads every step: u^n, u^{n-1} and q, plus the image's FP32
+// partial sums in imaging mode (d2 snapshots and the new field are touched
+// once).
 double resident_bytes(const SweepArgs &a, int mode)
 {
-    return (double)a.nx * (double)a.sxy * (mode == kImaging ? 20.0 : 12.0);
+    return (double)a.nx * (double)a.sxy * (mode == kImaging ? 16.0 : 12.0);
 }
 
 // Above this, loads of once-per-step data are non-temporal.  Measured on
@@ -355,7 +356,8 @@ struct Layout {
     float *ckpt = nullptr;          // [nck][2][N]
     int nck = 0;
     float *seg = nullptr;           // [K][N] second differences
-    double *g = nullptr;            // [N]
+    double *g = nullptr;            // [N] the image (FP64)
+    float *gp = nullptr;            // [N] its FP32 partial sums (kImageFlush steps at most)
     float *traces = nullptr;        // [nt][nr]
     float *resid = nullptr;         // [nt][nr]
     size_t bytes = 0;
@@ -408,6 +410,7 @@ Layout layout(void *ws, const Dims &d, int64_t nt, const PtsSpec &S, const PtsSp
         L.ckpt = cv.take<float>((size_t)std::max(L.nck, 1) * 2 * d.Np);
         L.seg = cv.take<float>((size_t)std::max(1, (int)std::min<int64_t>(K, std::max<int64_t>(nt, 1))) * d.Np);
         L.g = cv.take<double>(d.Np);
+        L.gp = cv.take<float>(d.Np);
         L.traces = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
         L.resid = cv.take<float>((size_t)std::max<int64_t>(nt * nr, 1));
     }
@@ -1276,7 +1279,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         a.d2 = c.L.seg;
         a.dslot0 = so.dslot_first + (int64_t)so.ddir * s;
         a.ddir = so.ddir;
-        a.g = c.L.g;
+        a.g = c.L.gp;
         // an injected table no chunk can stage: the tiled pass runs without it
         // in the plain mode and the untiled path's injection, recording and
         // second-difference or imaging kernels follow (its own order); only
@@ -2086,7 +2089,11 @@ void grad_issue(GradJob &j)
     adj.rec_out = nullptr;
     {
         double *g = c.L.g;
-        c.ex.call([g, N](hipStream_t s) { return launch_zero(g, N * 8, s); });
+        float *gp = c.L.gp;
+        c.ex.call([g, gp, N](hipStream_t s) {
+            hipError_t e = launch_zero(g, N * 8, s);
+            return e == hipSuccess ? launch_zero(gp, N * 4, s) : e;
+        });
     }
     float *Aa[4] = {c.L.fields[5], c.L.fields[6], c.L.fields[7], c.L.fields[8]};
     State sa{Aa[0], Aa[1], {Aa[2], Aa[3], nullptr}, 2};
@@ -2118,12 +2125,26 @@ void grad_issue(GradJob &j)
             advance(c, sf, k0, k1 - k0, fo);
         }
         c.base = adj;
-        StepOpts ao;
-        ao.mode = kImaging;
-        // adjoint step n produces lambda^{nt-n}; first step here n = nt - k1 -> slot k1 - k0 - 1
-        ao.dslot_first = k1 - k0 - 1;
-        ao.ddir = -1;
-        advance(c, sa, c.nt - k1, k1 - k0, ao);
+        // adjoint step n produces lambda^{nt-n}, imaged with the second
+        // difference in slot k1 - k0 - 1 - (n - (nt - k1)).  The FP32 partial
+        // sums are added into the image after every step n with n + 1 a
+        // multiple of kImageFlush, and after the last: the same blocks of
+        // steps for every checkpoint interval, so every storage choice rounds
+        // alike
+        for (int64_t n = c.nt - k1; n < c.nt - k0;) {
+            const int64_t end = std::min<int64_t>((n / kImageFlush + 1) * kImageFlush, c.nt - k0);
+            StepOpts ao;
+            ao.mode = kImaging;
+            ao.dslot_first = k1 - k0 - 1 - (n - (c.nt - k1));
+            ao.ddir = -1;
+            advance(c, sa, n, end - n, ao);
+            n = end;
+            if (n % kImageFlush == 0 || n == c.nt) {
+                double *g = c.L.g;
+                float *gp = c.L.gp;
+                c.ex.call([gp, g, N](hipStream_t s) { return launch_flush_image(gp, g, N, s); });
+            }
+        }
     }
     c.base = saved;
     {

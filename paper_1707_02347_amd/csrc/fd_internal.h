@@ -75,7 +75,8 @@ struct SweepArgs {
     float *d2;
     int64_t dslot0;
     int ddir;
-    double *g;        // imaging accumulator (FP64, N)
+    float *g;         // the image's partial sums (FP32, N) over at most kImageFlush
+                      // steps, then added into the FP64 image
     const float *bs;  // Born: scattering coefficient 2 dv / v (N); d2 slot dslot0 holds
                       // the background's second difference
     const float *u0b; // fused Born: the perturbation's u^n and u^{n-1} (o2 receives
@@ -121,6 +122,15 @@ struct SweepArgs {
     const int32_t *ptab;
 };
 constexpr int kPlaneTab = 8;  // int32 slots per plane of SweepArgs::ptab
+
+// The imaging condition's sum over time steps is carried in FP32 over at most
+// this many consecutive adjoint steps and then added into the FP64 image: the
+// FP32 partial sum costs at most this many roundings of its own magnitude
+// (about 4e-6 relative, against the ~1e-7 of the FP32 wavefields' terms
+// themselves), and reading and writing 4 instead of 8 bytes per point and step
+// takes 8 of the imaging pass's 36 bytes per point-step (the flush costs 24
+// bytes per point once per block).
+constexpr int kImageFlush = 64;
 
 // Point entries x time levels a workgroup can stage in LDS, the configurations
 // that can (the others would spill registers), and the table size below which
@@ -205,8 +215,10 @@ hipError_t launch_record(const SweepArgs &a, const float *field, int step, hipSt
 hipError_t launch_entry_x(const PointTable &t, int nx, int32_t *xe, hipStream_t s);
 hipError_t launch_save_d2(const SweepArgs &a, const float *unew, const float *ucur,
                           const float *uprev, float *d2, hipStream_t s);
-hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, double *g,
+hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, float *g,
                           hipStream_t s);
+// The FP64 image g += the partial sums part, which are then cleared.
+hipError_t launch_flush_image(float *part, double *g, int64_t n, hipStream_t s);
 
 // Preparation / reduction kernels.
 // q = v^2 dt^2 from the dense caller layout (rows of nz) into the padded

@@ -182,18 +182,33 @@ hipError_t launch_save_d2(const SweepArgs &a, const float *unew, const float *uc
     return hipGetLastError();
 }
 
-__global__ void k_imaging(const float *lam, const float *d2, double *g, int64_t n)
+__global__ void k_imaging(const float *lam, const float *d2, float *g, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        g[i] = fma((double)lam[i], (double)d2[i], g[i]);
+        g[i] = fmaf(lam[i], d2[i], g[i]);
 }
 
-hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, double *g,
+hipError_t launch_imaging(const SweepArgs &a, const float *lam, const float *d2, float *g,
                           hipStream_t s)
 {
     const int64_t n = (int64_t)a.nx * a.sxy;
     hipLaunchKernelGGL(k_imaging, dim3(4096), dim3(256), 0, s, lam, d2, g, n);
+    return hipGetLastError();
+}
+
+__global__ void k_flush_image(float *part, double *g, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        g[i] += (double)part[i];
+        part[i] = 0.0f;
+    }
+}
+
+hipError_t launch_flush_image(float *part, double *g, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flush_image, dim3(4096), dim3(256), 0, s, part, g, n);
     return hipGetLastError();
 }
 

@@ -102,18 +102,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, in
                                              valid ? (int)(uint32_t)nbytes : 0, 0x00020000);
 }
 
-template <int CP = kKeep>
-__device__ __forceinline__ double bload64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, CP));
-}
-
-template <int CP = kKeep>
-__device__ __forceinline__ void bstore64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, double v)
-{
-    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)byte_off, 0, CP);
-}
 
 template <int M, int T, int PY, int NW, int MODE, bool ISO, bool NTL, bool PS>
 struct StreamKernel {
@@ -201,9 +189,9 @@ struct StreamKernel {
         float halo[G::HS];
         float up1[PY];
         float q[T][PY];
-        // imaging: the FP64 accumulator at level 1's plane and the saved second
-        // differences at every level's plane
-        double g[IMG ? PY : 1];
+        // imaging: the image's partial sums at level 1's plane and the saved
+        // second differences at every level's plane
+        float g[IMG ? PY : 1];
         float d2[IMG ? T : 1][IMG ? PY : 1];
         // Born: the scattering coefficient and the background's second
         // difference at level 1's plane
@@ -372,12 +360,12 @@ struct StreamKernel {
 #pragma unroll
                 for (int j = 0; j < QS; ++j) qu[t][r][j] = 0.0f;
 
-        double acc[(MODE == kImaging) ? PY : 1][(MODE == kImaging) ? G::AQ : 1];
+        float acc[(MODE == kImaging) ? PY : 1][(MODE == kImaging) ? G::AQ : 1];
         if constexpr (MODE == kImaging) {
 #pragma unroll
             for (int r = 0; r < PY; ++r)
 #pragma unroll
-                for (int j = 0; j < G::AQ; ++j) acc[r][j] = 0.0;
+                for (int j = 0; j < G::AQ; ++j) acc[r][j] = 0.0f;
         }
 
         const int ibeg = th.x0 - T * M;
@@ -533,12 +521,6 @@ struct StreamKernel {
     {
         return th.core[r] ? th.bo[r] : kOutside;
     }
-    // The same for the FP64 accumulator plane (8-byte elements; the planner
-    // keeps ny nz < 2^28, so 2 bo < 2^31).
-    __device__ static __forceinline__ uint32_t out_off64(const Thread &th, int r)
-    {
-        return th.core[r] ? 2u * th.bo[r] : kOutside;
-    }
 
     // Plane at stream position i.
     __device__ static __forceinline__ int plane(const Thread &th, int i)
@@ -604,9 +586,9 @@ struct StreamKernel {
             // only planes this chunk owns are read (and later written); offsets
             // of points outside the output tile are beyond the plane
             const bool o1 = c1 >= th.x0 && c1 < th.xend;
-            const auto rg = span_rsrc(a.g + (int64_t)(o1 ? c1 : 0) * a.sxy, a.sxy * 8, o1);
+            const auto rg = span_rsrc(a.g + (int64_t)(o1 ? c1 : 0) * a.sxy, a.sxy * 4, o1);
 #pragma unroll
-            for (int r = 0; r < PY; ++r) P.g[r] = bload64<LP>(rg, out_off64(th, r));
+            for (int r = 0; r < PY; ++r) P.g[r] = bload<LP>(rg, out_off(th, r));
             const int64_t N = (int64_t)a.nx * a.sxy;
 #pragma unroll
             for (int t = 1; t <= T; ++t) {
@@ -884,15 +866,15 @@ struct StreamKernel {
         if constexpr (MODE == kImaging) {
             // g (level 1's plane) and d2 were loaded with this iteration's other
             // inputs; points outside the output tile read 0 and are not stored
-            const auto rg = span_rsrc(a.g + (int64_t)(own ? c : 0) * a.sxy, a.sxy * 8, own);
+            const auto rg = span_rsrc(a.g + (int64_t)(own ? c : 0) * a.sxy, a.sxy * 4, own);
             constexpr int J = (T - t) * M;
 #pragma unroll
             for (int r = 0; r < PY; ++r) {
-                double base;
+                float base;
                 if constexpr (t == 1) base = P.g[r];
                 else base = acc[r][J];
-                const double nv = fma((double)out[r], (double)P.d2[t - 1][r], base);
-                if constexpr (t == T) bstore64<LP>(rg, out_off64(th, r), nv);
+                const float nv = fmaf(out[r], P.d2[t - 1][r], base);
+                if constexpr (t == T) bstore<LP>(rg, out_off(th, r), nv);
                 else acc[r][J] = nv;
             }
         }

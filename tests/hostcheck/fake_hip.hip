@@ -301,7 +301,7 @@ void check_sweep(const Ctx &c, const KInfo &k, const SweepArgs &a, int ps_kernel
                   "level %d second-difference slot %lld outside the buffer", t, (long long)slot);
         }
     }
-    if (MODE == fdw::kImaging) CHECK(in_dev(a.g, F * 2), "imaging accumulator outside the buffers");
+    if (MODE == fdw::kImaging) CHECK(in_dev(a.g, F), "imaging partial sums outside the buffers");
     // staged point walks: every chunk's entries (with the time block's overlap
     // planes) within the LDS capacity of the staged kernel form
     if (ps_kernel) {
