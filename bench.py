@@ -539,13 +539,15 @@ def main():
                     help="run the autotuner on every workload shape and write its choices to PATH")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a plain 1 GiB device copy (calibrates the HBM byte counters)")
-    ap.add_argument("--kernel-only", choices=["cfg3", "cfg3-adjoint", "cfg2", "tblock-so8", "born", "sinc", "batch"],
+    ap.add_argument("--kernel-only", choices=["cfg3", "cfg3-adjoint", "cfg2", "tblock-so8", "born", "sinc", "batch",
+                                              "gradient"],
                     default=None,
                     help="only short runs of one workload, for profiling: cfg3 (512^3 so 16, whole "
                          "sweeps), cfg3-adjoint (its adjoint, whole sweeps), cfg2 (256^3 so 8, whole "
                          "sweeps), tblock-so8 (512^3 so 8: T = 1, overlapped T = 2, exchange T = 2), born (Born modelling "
                          "on the 256^3 grid, 256 receivers), sinc (the 256^3 sweep with windowed-sinc "
-                         "points, r = 4) or batch (the 32-shot forward batch)")
+                         "points, r = 4), batch (the 32-shot forward batch) or gradient (the 256^3 so-8 "
+                         "gradient, 200 steps, checkpoints every 50)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -723,6 +725,17 @@ def kernel_only(args):
         cs = workload("cfg2")
         for _ in range(n):
             _sweep(cs, launch_options("cfg2"))
+    elif what == "gradient":
+        # the gradient workload's kernels (checkpointed forward, recomputation
+        # saving second differences, adjoint with imaging, image flushes) over
+        # 200 steps; the residual's values do not change the kernels' cost
+        cs = workload("cfg4")
+        nt = 200
+        g = torch.Generator(device="cuda").manual_seed(4)
+        d_obs = 1e-3 * torch.randn((nt, len(cs["rec"])), generator=g, device="cuda")
+        for _ in range(n):
+            api.gradient(cs["v"], cs["h"], cs["so"], nt, cs["dt"], cs["src"], cs["amp"][:nt].contiguous(), cs["rec"],
+                         d_obs, sponge=cs["sponge"], vref=cs["vref"], ckpt_every=50, **launch_options("cfg4"))
     elif what == "cfg3-adjoint":
         cs = workload("cfg3")
         rec, res = adjoint_case(cs)
