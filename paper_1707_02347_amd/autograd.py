@@ -6,7 +6,8 @@ Reverse mode (backward) returns
     (fd_vjp: forward checkpoints every ``geom.ckpt_every`` steps and segment
     recomputation, or the whole time axis stored, or ``"auto"``: the library
     picks one for the device's free memory; adjoint sweep, zero-lag imaging
-    condition accumulated in FP64, dL/dm -> dL/dv = dL/dm * (-2 / v^3));
+    condition summed in FP32 over 64-step blocks into an FP64 image,
+    dL/dm -> dL/dv = dL/dm * (-2 / v^3));
   * dL/dwavelet = F^T (dL/dd), the adjoint sweep read at the sources
     (fd_adjoint), since the traces are linear in the wavelet.
 Forward mode (jvp, with ``torch.autograd.forward_ad`` dual tensors) returns

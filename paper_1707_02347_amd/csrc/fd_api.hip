@@ -195,8 +195,8 @@ int make_dims(const fd_grid *g, Dims &d)
     d.nzp = (int)((n3[2] + 31) / 32 * 32);
     d.Np = n3[0] * n3[1] * (int64_t)d.nzp;
     // one (y, z) plane must stay below 2^28 points: kernels address a plane
-    // with 32-bit byte offsets (8-byte elements for the FP64 imaging
-    // accumulator) and mark points outside the grid with offset 2^31
+    // with 32-bit byte offsets (4-byte elements) and mark points outside the
+    // grid with offset 2^31
     if (n3[1] * (int64_t)d.nzp >= ((int64_t)1 << 28)) return FD_EINVAL;
     for (int a = 0; a < 3; ++a) {
         d.h[a] = h3[a];
