@@ -53,17 +53,25 @@ namespace fdw {
 // Cache policy of the exchanged level (device-coherent: SC1).
 constexpr int kCoherent = 16;
 
-// Level 2 lags level 1 by M + E planes; the E extra planes are slack that lets
-// a neighbour's counter run a few iterations late without a wait.
-constexpr int kWaveLag = 11;
-constexpr int wave_extra(int M) { return M >= kWaveLag ? 0 : kWaveLag - M; }
-
 // Prefetch distance: iteration i issues the loads of iteration i + kWaveAhead.
 // Measured at 512^3 so 8 (2 x 8 tiles, GPts/s): distance 1 317, 2 327, 3 339,
-// 4 329, 5 328 (each with the lag the counters need); the lag beyond that
-// bound gains nothing.
+// 4 329, 5 328, each with the shortest lag the counters allow (2D + 3); at
+// so 4, distance 2 (lag 7) 310 against distance 3 (lag 11) 387.
 constexpr int kWaveAhead = 3;
-static_assert(kWaveLag >= 2 * kWaveAhead + 3, "level 2 must trail level 1 by more than the counters lag");
+
+// Level 2 lags level 1 by M + E planes; the E extra planes are slack that lets
+// a neighbour's counter run that many iterations late without a wait.  More
+// slack costs registers (every queue holds 2M + 1 + E planes) and pays while
+// they last.  Measured at 512^3 (2 x 8 tiles, GPts/s): so 4, lag 11 / 13 / 15 /
+// 17 / 19: 389 / 399 / 411 / 425 / 425; so 8, lag 11 / 15 / 17 / 19: 350 / 363 /
+// 363 / 364.  Tiles of two rows per thread up to M = 4 take the long lag; the
+// other shapes keep the short one (their queues would not fit the registers).
+constexpr int kWaveLagShort = 11;
+constexpr int kWaveLagLong = 17;
+static_assert(kWaveLagShort >= 2 * kWaveAhead + 3 && kWaveLagLong >= 2 * kWaveAhead + 3,
+              "level 2 must trail level 1 by more than the counters lag");
+constexpr int wave_lag(int M, int PY) { return (M <= 4 && PY <= 2) ? kWaveLagLong : kWaveLagShort; }
+constexpr int wave_extra(int M, int PY) { return M >= wave_lag(M, PY) ? 0 : wave_lag(M, PY) - M; }
 
 // Bound of one wait, in polls of the neighbours' counters (a poll is one
 // device-coherent load round trip plus a short sleep).
@@ -74,7 +82,7 @@ struct WaveKernel {
     static constexpr int NT = 64 * NW;       // threads per workgroup
     static constexpr int RY = NW * PY;       // tile rows (y)
     static constexpr int RZ = 64;            // tile columns (z)
-    static constexpr int E = wave_extra(M);
+    static constexpr int E = wave_extra(M, PY);
     static constexpr int Q = 2 * M + 1 + E;  // queue length of u^n and of level 1 along x
     static constexpr int QQ = M + E + 1;     // queue of q: level 1's plane down to level 2's
     // The x loop is unrolled by U = D + 1 (D the prefetch distance), with U

@@ -15,8 +15,9 @@ adversarial and random schedules, checking:
   once every neighbour's ring loads of u^n at plane c have completed;
 * progress: some workgroup can always move, and every one finishes.
 
-The constants (prefetch distance, level lag, compiled radii) are read from
-the kernel sources.  Mutations of the protocol (a count published before the
+The constants (prefetch distance, the short and long level lags, compiled
+radii) are read from the kernel sources; every radius is checked with both
+lags.  Mutations of the protocol (a count published before the
 first complete iteration, a count one too high, a lag one plane short of
 2D + 3) must each be caught, so the checker has teeth.
 """
@@ -41,7 +42,7 @@ def compiled_radii():
 
 
 D = constant("kWaveAhead")
-LAG = constant("kWaveLag")
+LAGS = (constant("kWaveLagShort"), constant("kWaveLagLong"))
 MASK = (1 << 32) - 1
 EPOCH = 7
 
@@ -53,9 +54,8 @@ class Violation(AssertionError):
 class Model:
     """One pass over an nty x ntz grid of tiles, nx planes along x."""
 
-    def __init__(self, M, nx, nty=3, ntz=3, lag=None, publish="kernel"):
+    def __init__(self, M, nx, nty=3, ntz=3, lag=LAGS[0], publish="kernel"):
         self.M, self.nx = M, nx
-        lag = LAG if lag is None else lag
         self.E = max(lag - M, 0)
         self.publish_rule = publish
         self.ibeg, self.iend = M, nx + 2 * M + self.E
@@ -212,23 +212,24 @@ def lockstep_order(model):
 def schedules(victims):
     out = [lockstep_order]
     out += [random_order(s) for s in range(6)]
-    out += [starve_order(v, h) for v in victims for h in range(2 * (LAG + D) + 4)]
+    out += [starve_order(v, h) for v in victims for h in range(2 * (max(LAGS) + D) + 4)]
     return out
 
 
+@pytest.mark.parametrize("lag", LAGS)
 @pytest.mark.parametrize("M", compiled_radii())
-def test_protocol_is_safe_and_live_for_every_compiled_radius(M):
-    assert LAG >= 2 * D + 3
-    nx = 3 * (2 * M + LAG)
+def test_protocol_is_safe_and_live_for_every_compiled_radius(M, lag):
+    assert lag >= 2 * D + 3
+    nx = 3 * (2 * M + lag)
     for order in schedules([(1, 1), (0, 0)]):
-        m = run(Model(M, nx), order)
+        m = run(Model(M, nx, lag=lag), order)
         assert m.done()
 
 
 def test_laggard_never_waits():
     """The workgroup furthest behind is never the one that waits."""
-    for M in compiled_radii():
-        m = Model(M, 40)
+    for M, lag in ((M, lag) for M in compiled_radii() for lag in LAGS):
+        m = Model(M, 40, lag=lag)
         m.prologue()
         rng = random.Random(M)
         while not m.done():
