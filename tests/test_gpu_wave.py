@@ -37,10 +37,14 @@ def run(cs, rec=None, src=None, **opts):
     (6, (33, 45, 77), (0, 0, 0)),
     (12, (41, 50, 90), (0, 0, 0)),
     (16, (52, 36, 140), (0, 0, 0)),
+    (2, (3, 40, 70), (0, 0, 0)),       # x extents shorter than the level lag
+    (4, (7, 33, 100), (0, 16, 2)),
+    (8, (9, 20, 64), (0, 8, 2)),
 ])
 def test_wave_equals_untiled(so, shape, tile):
     print(f"wave so {so} shape {shape} tile {tile}", flush=True)
-    cs = make_case(shape, so, 31, 5)  # an odd step count: the last pass is single-level
+    # an odd step count: the last pass is single-level; the sponge fits every axis
+    cs = make_case(shape, so, 31, min(5, min(shape) // 2))
     base = run(cs, rec=cs["rec"], variant=L.FD_VARIANT_NAIVE)
     out = run(cs, rec=cs["rec"], variant=L.FD_VARIANT_WAVE, tile=tile)
     cfg = api.last_config()
