@@ -565,7 +565,7 @@ int wave_plan(const Dims &d, const fd_options &eff, Plan &p)
 {
     if (eff.tblock != 0 && eff.tblock != 2) return FD_EINVAL;
     const bool iso = grid_iso(d);
-    // preference order from 512^3 sweeps: so 8 2 x 8 363 GPts/s, 2 x 4 341;
+    // preference order from 512^3 sweeps: so 8 2 x 8 380 GPts/s, 2 x 4 345;
     // 4 x 4 ran 20-35 % behind 2 x 8 (so 8 / so 16) in an earlier build, and
     // 1 x 16 (no longer compiled) 8 % behind
     static const int shapes[][2] = {{2, 8}, {2, 4}, {4, 4}};

@@ -27,16 +27,16 @@
 // vector memory operations complete in issue order, so by the barrier of
 // iteration k every store of iteration k - D - 1 and before has completed.
 // Thread 0 then stores the counter k - D ("iterations below k - D complete"),
-// also device-coherently, every second iteration; each counter has a
-// 256-byte line of its own.  A reader polls its neighbours' counters before
+// also device-coherently, every P-th iteration; each counter has a 256-byte
+// line of its own.  A reader polls its neighbours' counters before
 // issuing the ring loads they gate, and only when the values it last saw would
 // not admit them.
 //
 // Progress.  The host launches a pass only when all of its workgroups can be
 // resident at once (occupancy x compute units).  A workgroup at iteration i
-// waits only for neighbours to have reached iteration i + 2D + 2 - (M + E),
-// below its own (M + E >= 2D + 3): the workgroup furthest behind never waits,
-// so every wait ends.
+// waits only for neighbours to have reached iteration i + 2D + P - (M + E),
+// below its own (M + E >= 2D + P + 1): the workgroup furthest behind never
+// waits, so every wait ends.
 // Each wait is still bounded (kWaveSpin polls); a wait that runs out sets the
 // pass's error word, which every later wait checks, so a launch that somehow
 // did not run all of its workgroups at once ends with an error instead of a
@@ -68,10 +68,21 @@ constexpr int kWaveAhead = 3;
 // other shapes keep the short one (their queues would not fit the registers).
 constexpr int kWaveLagShort = 11;
 constexpr int kWaveLagLong = 17;
-static_assert(kWaveLagShort >= 2 * kWaveAhead + 3 && kWaveLagLong >= 2 * kWaveAhead + 3,
-              "level 2 must trail level 1 by more than the counters lag");
 constexpr int wave_lag(int M, int PY) { return (M <= 4 && PY <= 2) ? kWaveLagLong : kWaveLagShort; }
 constexpr int wave_extra(int M, int PY) { return M >= wave_lag(M, PY) ? 0 : wave_lag(M, PY) - M; }
+
+// Counters are published every P-th iteration (a device-coherent store in the
+// wave's in-order memory queue); the lag must cover the staler counts:
+// M + E >= 2D + P + 1.  Measured at 512^3 with the long lag (2 x 8 tiles,
+// GPts/s): P = 2 / 4 / 8: so 8 364 / 368-372 / 379-381, so 4 420 / 426-430 /
+// -; with the short lag P = 4 ran slower than P = 2 (so 4, 4 x 4 tiles: 306
+// against 320).
+constexpr int kWavePubShort = 2;
+constexpr int kWavePubLong = 8;
+static_assert(kWaveLagShort >= 2 * kWaveAhead + kWavePubShort + 1 &&
+                  kWaveLagLong >= 2 * kWaveAhead + kWavePubLong + 1,
+              "level 2 must trail level 1 by more than the counters lag");
+constexpr int wave_pub(int M, int PY) { return wave_lag(M, PY) == kWaveLagLong ? kWavePubLong : kWavePubShort; }
 
 // Bound of one wait, in polls of the neighbours' counters (a poll is one
 // device-coherent load round trip plus a short sleep).
@@ -83,6 +94,8 @@ struct WaveKernel {
     static constexpr int RY = NW * PY;       // tile rows (y)
     static constexpr int RZ = 64;            // tile columns (z)
     static constexpr int E = wave_extra(M, PY);
+    static constexpr int PUB = wave_pub(M, PY);  // counter publication interval P
+    static_assert((PUB & (PUB - 1)) == 0 && M + E >= 2 * kWaveAhead + PUB + 1, "lag too short for the interval");
     static constexpr int Q = 2 * M + 1 + E;  // queue length of u^n and of level 1 along x
     static constexpr int QQ = M + E + 1;     // queue of q: level 1's plane down to level 2's
     // The x loop is unrolled by U = D + 1 (D the prefetch distance), with U
@@ -262,8 +275,8 @@ struct WaveKernel {
     {
         wait_for(a, th, flag, i + D);
         // poll again only if the counters last seen would not admit the next
-        // iteration's ring loads (in step with the neighbours, every second or
-        // third iteration): a poll is a device-coherent round trip, and the
+        // iteration's ring loads (in step with the neighbours, every few
+        // iterations): a poll is a device-coherent round trip, and the
         // loads issued after it complete only after it
         if (!__all(flag >= want_of(a, i + D + 1))) flag = poll(a, th);
         load(a, th, next, i + D);
@@ -469,12 +482,12 @@ struct WaveKernel {
         __syncthreads();
         // every wave has waited for this iteration's loads, issued D
         // iterations ago, after its stores of iteration i - D - 1: those
-        // stores, and all before them, are complete (stored every second
-        // iteration; the readers' slack covers the extra one).  Nothing is
+        // stores, and all before them, are complete (stored every P-th
+        // iteration; the readers' slack covers the rest).  Nothing is
         // stored while i - D < 1: a negative count would read as a huge one
         // in the counter's low word, i.e. as every plane of the pass stored
         // (the first iteration is i = M, below D for M < D).
-        if (threadIdx.x == 0 && (i & 1) == 0 && i > D)
+        if (threadIdx.x == 0 && (i & (PUB - 1)) == 0 && i > D)
             __hip_atomic_store(a.prog + (int64_t)kWaveProgStride * th.tile,
                                ((uint64_t)a.epoch << 32) | (uint32_t)(i - D), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

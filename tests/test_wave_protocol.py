@@ -15,11 +15,12 @@ adversarial and random schedules, checking:
   once every neighbour's ring loads of u^n at plane c have completed;
 * progress: some workgroup can always move, and every one finishes.
 
-The constants (prefetch distance, the short and long level lags, compiled
-radii) are read from the kernel sources; every radius is checked with both
-lags.  Mutations of the protocol (a count published before the
-first complete iteration, a count one too high, a lag one plane short of
-2D + 3) must each be caught, so the checker has teeth.
+The constants (prefetch distance, the short and long level lags with their
+counter publication intervals, compiled radii) are read from the kernel
+sources; every radius is checked with both pairs.  Mutations of the protocol
+(a count published before the first complete iteration, a count one too high,
+a lag one plane short of 2D + 3, an interval too coarse for its lag) must each
+be caught, so the checker has teeth.
 """
 import os
 import random
@@ -43,6 +44,7 @@ def compiled_radii():
 
 D = constant("kWaveAhead")
 LAGS = (constant("kWaveLagShort"), constant("kWaveLagLong"))
+PUBS = (constant("kWavePubShort"), constant("kWavePubLong"))  # publication interval of each lag
 MASK = (1 << 32) - 1
 EPOCH = 7
 
@@ -54,8 +56,8 @@ class Violation(AssertionError):
 class Model:
     """One pass over an nty x ntz grid of tiles, nx planes along x."""
 
-    def __init__(self, M, nx, nty=3, ntz=3, lag=LAGS[0], publish="kernel"):
-        self.M, self.nx = M, nx
+    def __init__(self, M, nx, nty=3, ntz=3, lag=LAGS[0], pub=PUBS[0], publish="kernel"):
+        self.M, self.nx, self.pub = M, nx, pub
         self.E = max(lag - M, 0)
         self.publish_rule = publish
         self.ibeg, self.iend = M, nx + 2 * M + self.E
@@ -76,7 +78,7 @@ class Model:
     # -- the protocol's arithmetic, as the kernel states it
     def publish(self, i):
         """Counter a workgroup stores at the barrier of iteration i, or None."""
-        if i & 1:
+        if i % self.pub:
             return None
         if self.publish_rule == "kernel":
             return (EPOCH << 32) | (i - D) if i > D else None
@@ -216,20 +218,20 @@ def schedules(victims):
     return out
 
 
-@pytest.mark.parametrize("lag", LAGS)
+@pytest.mark.parametrize("lag,pub", list(zip(LAGS, PUBS)))
 @pytest.mark.parametrize("M", compiled_radii())
-def test_protocol_is_safe_and_live_for_every_compiled_radius(M, lag):
-    assert lag >= 2 * D + 3
+def test_protocol_is_safe_and_live_for_every_compiled_radius(M, lag, pub):
+    assert lag >= 2 * D + pub + 1
     nx = 3 * (2 * M + lag)
     for order in schedules([(1, 1), (0, 0)]):
-        m = run(Model(M, nx, lag=lag), order)
+        m = run(Model(M, nx, lag=lag, pub=pub), order)
         assert m.done()
 
 
 def test_laggard_never_waits():
     """The workgroup furthest behind is never the one that waits."""
-    for M, lag in ((M, lag) for M in compiled_radii() for lag in LAGS):
-        m = Model(M, 40, lag=lag)
+    for M, (lag, pub) in ((M, lp) for M in compiled_radii() for lp in zip(LAGS, PUBS)):
+        m = Model(M, 40, lag=lag, pub=pub)
         m.prologue()
         rng = random.Random(M)
         while not m.done():
@@ -268,3 +270,10 @@ def test_mutation_short_lag_is_caught():
     # a lag below 2D + 3 lets neighbours wait on each other
     msg = find_violation(lambda: Model(4, 30, lag=2 * D + 2))
     assert msg is not None
+
+
+def test_mutation_interval_too_coarse_for_the_lag_is_caught():
+    # the long interval with the short lag: M + E < 2D + P + 1
+    assert LAGS[0] < 2 * D + PUBS[1] + 1
+    msg = find_violation(lambda: Model(4, 40, lag=LAGS[0], pub=PUBS[1]))
+    assert msg is not None and "no workgroup can move" in msg
