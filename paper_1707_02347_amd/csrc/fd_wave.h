@@ -62,27 +62,34 @@ constexpr int kWaveAhead = 3;
 // Level 2 lags level 1 by M + E planes; the E extra planes are slack that lets
 // a neighbour's counter run that many iterations late without a wait.  More
 // slack costs registers (every queue holds 2M + 1 + E planes) and pays while
-// they last.  Measured at 512^3 (2 x 8 tiles, GPts/s): so 4, lag 11 / 13 / 15 /
-// 17 / 19: 389 / 399 / 411 / 425 / 425; so 8, lag 11 / 15 / 17 / 19: 350 / 363 /
-// 363 / 364.  Tiles of two rows per thread up to M = 4 take the long lag; the
-// other shapes keep the short one (their queues would not fit the registers).
+// they last.  Measured at 512^3 (2 x 8 tiles, GPts/s), counters every second
+// iteration: so 4, lag 11 / 13 / 15 / 17 / 19: 389 / 399 / 411 / 425 / 425;
+// so 8, lag 11 / 15 / 17 / 19: 350 / 363 / 363 / 364.  Every eighth
+// iteration (below): so 4, lag 17 / 19: 428 / 441; so 8: 378 / 367.  Tiles of
+// two rows per thread take the long lags up to M = 4; the other shapes keep
+// the short one (their queues would not fit the registers).
 constexpr int kWaveLagShort = 11;
-constexpr int kWaveLagLong = 17;
-constexpr int wave_lag(int M, int PY) { return (M <= 4 && PY <= 2) ? kWaveLagLong : kWaveLagShort; }
+constexpr int kWaveLagLong = 17;    // two-row tiles, M = 3, 4
+constexpr int kWaveLagLonger = 19;  // two-row tiles, M <= 2
+constexpr int wave_lag(int M, int PY)
+{
+    return PY > 2 || M > 4 ? kWaveLagShort : M > 2 ? kWaveLagLong : kWaveLagLonger;
+}
 constexpr int wave_extra(int M, int PY) { return M >= wave_lag(M, PY) ? 0 : wave_lag(M, PY) - M; }
 
 // Counters are published every P-th iteration (a device-coherent store in the
 // wave's in-order memory queue); the lag must cover the staler counts:
-// M + E >= 2D + P + 1.  Measured at 512^3 with the long lag (2 x 8 tiles,
-// GPts/s): P = 2 / 4 / 8: so 8 364 / 368-372 / 379-381, so 4 420 / 426-430 /
-// -; with the short lag P = 4 ran slower than P = 2 (so 4, 4 x 4 tiles: 306
-// against 320).
+// M + E >= 2D + P + 1.  Measured at 512^3 with lag 17 (2 x 8 tiles, GPts/s):
+// P = 2 / 4 / 8: so 8 364 / 368-372 / 379-381, so 4 420 / 426-430 / 428;
+// P = 16 (lag 23 / 25, M = 2 only: M = 4 spills): so 4 414 / 427.  With the
+// short lag P = 4 ran slower than P = 2 (so 4, 4 x 4 tiles: 306 against 320).
 constexpr int kWavePubShort = 2;
-constexpr int kWavePubLong = 8;
+constexpr int kWavePubLong = 8;  // with either long lag
 static_assert(kWaveLagShort >= 2 * kWaveAhead + kWavePubShort + 1 &&
-                  kWaveLagLong >= 2 * kWaveAhead + kWavePubLong + 1,
+                  kWaveLagLong >= 2 * kWaveAhead + kWavePubLong + 1 &&
+                  kWaveLagLonger >= 2 * kWaveAhead + kWavePubLong + 1,
               "level 2 must trail level 1 by more than the counters lag");
-constexpr int wave_pub(int M, int PY) { return wave_lag(M, PY) == kWaveLagLong ? kWavePubLong : kWavePubShort; }
+constexpr int wave_pub(int M, int PY) { return wave_lag(M, PY) > kWaveLagShort ? kWavePubLong : kWavePubShort; }
 
 // Bound of one wait, in polls of the neighbours' counters (a poll is one
 // device-coherent load round trip plus a short sleep).

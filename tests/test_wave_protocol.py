@@ -15,9 +15,9 @@ adversarial and random schedules, checking:
   once every neighbour's ring loads of u^n at plane c have completed;
 * progress: some workgroup can always move, and every one finishes.
 
-The constants (prefetch distance, the short and long level lags with their
-counter publication intervals, compiled radii) are read from the kernel
-sources; every radius is checked with both pairs.  Mutations of the protocol
+The constants (prefetch distance, the level lags with their counter
+publication intervals, compiled radii) are read from the kernel sources;
+every radius is checked with every pair.  Mutations of the protocol
 (a count published before the first complete iteration, a count one too high,
 a lag one plane short of 2D + 3, an interval too coarse for its lag) must each
 be caught, so the checker has teeth.
@@ -43,8 +43,8 @@ def compiled_radii():
 
 
 D = constant("kWaveAhead")
-LAGS = (constant("kWaveLagShort"), constant("kWaveLagLong"))
-PUBS = (constant("kWavePubShort"), constant("kWavePubLong"))  # publication interval of each lag
+LAGS = (constant("kWaveLagShort"), constant("kWaveLagLong"), constant("kWaveLagLonger"))
+PUBS = (constant("kWavePubShort"), constant("kWavePubLong"), constant("kWavePubLong"))  # interval of each lag
 MASK = (1 << 32) - 1
 EPOCH = 7
 
