@@ -135,7 +135,10 @@ extern "C" {
                                 Plain forward and adjoint passes only: gradient and Born
                                 passes, passes whose point tables are injected or recorded
                                 separately, batches and single-step tails use the other
-                                variants' kernels. */
+                                variants' kernels; so do, when the plan is automatic (a
+                                cached choice), passes with more than 64 source and
+                                receiver entries (the workgroups owning them walk them on
+                                their planes, and their neighbours wait for them). */
 
 /* ------------------------------------------------------------------ flags */
 #define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */

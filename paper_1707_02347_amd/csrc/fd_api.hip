@@ -440,6 +440,7 @@ struct Plan {
     int loads;        // cache policy of once-per-step loads: -1 automatic, 0 keep, 1 stream
     bool split = false;  // two-level plain passes split into trapezoids along x
     bool wave = false;   // two-level plain passes without redundant halos (fd_wave.h)
+    bool wave_auto = false;  // ... chosen by the automatic plan (see kWaveAutoEntries)
 };
 
 std::mutex g_tune_mu;
@@ -641,6 +642,7 @@ int make_plan(const Dims &d, const fd_options *o, Plan &p)
     }
     if (eff.variant == FD_VARIANT_WAVE) {
         const int rc = wave_plan(d, eff, p);
+        if (rc == FD_OK) p.wave_auto = automatic;
         // a cached choice this device cannot run (fewer compute units than the
         // one it was tuned on) falls back to the default plan
         if (rc != FD_EUNSUPPORTED || !automatic) return rc;
@@ -1098,6 +1100,15 @@ constexpr int kHeavySpan = 32;
 // differences or image, whose alternative re-reads fields.
 constexpr int kRouteInjPlain = 256;
 
+// An automatic plan runs a pass as an exchange pass (fd_wave.h) only with at
+// most this many point entries.  The workgroup that owns points walks them on
+// each of its planes, and its neighbours, which wait for its level 1, then run
+// at its pace: at 512^3 with a line of 256 receivers along x (every entry in
+// one tile's column) the exchange form ran 314 GPts/s at so 8 against 336 for
+// the single-level kernel (349 against 333 at so 4); with 16 receivers 378
+// against 338 (436 against 360).
+constexpr int64_t kWaveAutoEntries = 64;
+
 bool heavy_table(const Ctx &c, const PointTable &t)
 {
     if (t.cnt <= kPtsCap) return false;
@@ -1313,7 +1324,8 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // left, issued immediately, whose point tables need no separate route
         // (such tables and single-step tails take the passes below)
         if (c.plan.wave && !c.ex.rec && so.mode == kPlain && !isep && !rsep && nsteps - s >= 2 &&
-            a.inj.xptr == c.L.src.xptr && a.rec.xptr == c.L.rec.xptr && a.ptab == c.L.ptab) {
+            a.inj.xptr == c.L.src.xptr && a.rec.xptr == c.L.rec.xptr && a.ptab == c.L.ptab &&
+            !(c.plan.wave_auto && (int64_t)a.inj.cnt + a.rec.cnt > kWaveAutoEntries)) {
             const KernelKey &k = c.plan.key;
             a.u0 = st.cur;
             a.um = st.prev;

@@ -67,3 +67,25 @@ def test_tuner_keeps_fixed_fields(tmp_path, monkeypatch):
     base = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
     out = run(v, h, so, nt, dt, src, rec, amp, **tuned)
     assert torch.equal(out["rec"], base["rec"])
+
+
+def test_automatic_exchange_plan_runs_point_heavy_passes_single_level(tmp_path, monkeypatch):
+    """A cached choice of the exchange form (the tuner run with the variant
+    fixed) serves automatic plans, but their passes with more than 64 point
+    entries run single-level: the workgroup walking those entries would hold
+    back its neighbours, which wait for its level 1.  An explicit request keeps
+    the exchange passes.  Every run equals the untiled sweep bit for bit."""
+    monkeypatch.setenv("FD_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    shape = (96, 48, 70)  # a shape no other test tunes: the tuned choice stays in this process
+    v, h, so, nt, dt, src, _, amp = case(shape, so=8)
+    tuned = api.autotune(tuple(v.shape), h, so, dt, sponge=6, vref=4500.0, variant=L.FD_VARIANT_WAVE)
+    assert tuned["variant"] == L.FD_VARIANT_WAVE
+    for nrec, expect in ((12, L.FD_VARIANT_WAVE), (80, L.FD_VARIANT_STREAM)):
+        rec = synth.receiver_line(shape, nrec, depth=8)
+        base = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
+        auto = run(v, h, so, nt, dt, src, rec, amp)
+        assert api.last_config()["variant"] == expect, nrec
+        assert torch.equal(auto["rec"], base["rec"]) and torch.equal(auto["u"], base["u"])
+        explicit = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_WAVE, tile=tuned["tile"])
+        assert api.last_config()["variant"] == L.FD_VARIANT_WAVE
+        assert torch.equal(explicit["rec"], base["rec"]) and torch.equal(explicit["u"], base["u"])
