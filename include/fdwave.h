@@ -136,9 +136,10 @@ extern "C" {
                                 passes, passes whose point tables are injected or recorded
                                 separately, batches and single-step tails use the other
                                 variants' kernels; so do, when the plan is automatic (a
-                                cached choice), passes with more than 64 source and
-                                receiver entries (the workgroups owning them walk them on
-                                their planes, and their neighbours wait for them). */
+                                cached choice), passes with more than 64 injected entries
+                                or more than 64 receiver entries beyond the first of each
+                                x-plane (the workgroups holding them walk them through
+                                memory, and their neighbours wait for them). */
 
 /* ------------------------------------------------------------------ flags */
 #define FD_FLAG_NO_CFL_CHECK 1u   /* skip the max(v) read-back and stability check */

@@ -887,7 +887,8 @@ int check_position(const Dims &d, const double *pos)
 // Host staging of a table; kept alive until the copies are enqueued (pageable
 // copies are staged by the runtime before hipMemcpyAsync returns).
 void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs &b, int npts,
-                  std::vector<int32_t> *host_xptr, hipStream_t s)
+                  std::vector<int32_t> *host_xptr, hipStream_t s, std::vector<int32_t> *host_yz = nullptr,
+                  std::vector<int32_t> *host_id = nullptr)
 {
     std::vector<int32_t> xptr(d.nx + 1, 0), xe(ent.size()), yz(ent.size()), id(ent.size());
     std::vector<float> wt(ent.size());
@@ -920,6 +921,8 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
     }
     for (int x = 0; x < d.nx; ++x) xptr[x + 1] += xptr[x];
     if (host_xptr) *host_xptr = xptr;
+    if (host_yz) *host_yz = yz;
+    if (host_id) *host_id = id;
     FDW_HIP(hipMemcpyAsync(b.xptr, xptr.data(), xptr.size() * 4, hipMemcpyHostToDevice, s));
     if (!ent.empty()) {
         FDW_HIP(hipMemcpyAsync(b.xe, xe.data(), xe.size() * 4, hipMemcpyHostToDevice, s));
@@ -948,10 +951,14 @@ void upload_table(const Dims &d, const std::vector<Entry> &ent, const TableBufs 
 }
 
 // The per-plane table of passes without redundant halos: per x-plane the
-// sponge profile, the source and receiver entry ranges, and whether they are
-// non-empty (one vector load per iteration reads it, lane k holding slot k).
+// sponge profile, the source and receiver entry ranges, whether they are
+// non-empty, and the plane's first receiver entry (its node and its output
+// slot: an entry index when receivers interpolate, else the receiver's column)
+// (one vector load per iteration reads it, lane k holding slot k).
 void upload_planes(const Dims &d, const float *px, const std::vector<int32_t> &xs,
-                   const std::vector<int32_t> &xr, int32_t *dst, hipStream_t s)
+                   const std::vector<int32_t> &xr, int32_t *dst, hipStream_t s,
+                   const std::vector<int32_t> &ryz = {}, const std::vector<int32_t> &rid = {},
+                   bool rinterp = false)
 {
     std::vector<int32_t> t((size_t)d.nx * kPlaneTab, 0);
     for (int c = 0; c < d.nx; ++c) {
@@ -962,6 +969,10 @@ void upload_planes(const Dims &d, const float *px, const std::vector<int32_t> &x
         e[3] = xr.size() > (size_t)c + 1 ? xr[c] : 0;
         e[4] = xr.size() > (size_t)c + 1 ? xr[c + 1] : 0;
         e[5] = (e[2] > e[1] ? 1 : 0) | (e[4] > e[3] ? 2 : 0);
+        if (e[4] > e[3] && (size_t)e[3] < ryz.size() && (size_t)e[3] < rid.size()) {
+            e[6] = ryz[e[3]];
+            e[7] = rinterp ? e[3] : rid[e[3]];
+        }
     }
     FDW_HIP(hipMemcpyAsync(dst, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
     FDW_HIP(hipStreamSynchronize(s));
@@ -1049,6 +1060,7 @@ struct Ctx {
     Layout L;
     SweepArgs base;   // common launch arguments
     std::vector<int32_t> hxs, hxr;  // host copies of the point tables' plane pointers
+    int64_t rec_extra = 0;          // receiver entries beyond the first of each plane
     int ran_T = 0;    // deepest time block a pass of this call used (0: none yet)
     bool ran_split = false;  // a pass of this call ran split along x
     uint32_t wave_epoch = 0;  // passes without redundant halos issued so far
@@ -1101,12 +1113,16 @@ constexpr int kHeavySpan = 32;
 constexpr int kRouteInjPlain = 256;
 
 // An automatic plan runs a pass as an exchange pass (fd_wave.h) only with at
-// most this many point entries.  The workgroup that owns points walks them on
-// each of its planes, and its neighbours, which wait for its level 1, then run
-// at its pace: at 512^3 with a line of 256 receivers along x (every entry in
-// one tile's column) the exchange form ran 314 GPts/s at so 8 against 336 for
-// the single-level kernel (349 against 333 at so 4); with 16 receivers 378
-// against 338 (436 against 360).
+// most this many injected entries and this many receiver entries beyond the
+// first of each plane.  A plane's first receiver entry comes with the
+// per-plane table; every other entry is read from memory by the workgroups on
+// that plane, and a load there waits for all of their prefetches, so the
+// workgroup holding many entries slows down, and its neighbours, which wait
+// for its level 1, run at its pace.  At 512^3 with a line of 256 receivers
+// along x the exchange form ran 362 GPts/s at so 8 against 337 for the
+// single-level kernel (413 against 333 at so 4); before the first entry came
+// with the table, 314 at so 8.  Injecting at those 256 points (the adjoint):
+// 289 against 328.
 constexpr int64_t kWaveAutoEntries = 64;
 
 bool heavy_table(const Ctx &c, const PointTable &t)
@@ -1189,9 +1205,12 @@ int prepare(Ctx &c, const fd_grid *g, const float *v, const fd_points *inj, floa
     if (rc) return rc;
     rc = build_table(d, rec, er);
     if (rc) return rc;
+    std::vector<int32_t> ryz, rid;
     upload_table(d, es, c.L.src, inj ? inj->n : 0, &c.hxs, c.s);
-    upload_table(d, er, c.L.rec, rec ? rec->n : 0, &c.hxr, c.s);
-    upload_planes(d, prof.data(), c.hxs, c.hxr, c.L.ptab, c.s);
+    upload_table(d, er, c.L.rec, rec ? rec->n : 0, &c.hxr, c.s, &ryz, &rid);
+    upload_planes(d, prof.data(), c.hxs, c.hxr, c.L.ptab, c.s, ryz, rid, c.L.rec.interp);
+    c.rec_extra = 0;
+    for (size_t x = 0; x + 1 < c.hxr.size(); ++x) c.rec_extra += std::max(0, c.hxr[x + 1] - c.hxr[x] - 1);
 
     SweepArgs &a = c.base;
     std::memset(&a, 0, sizeof a);
@@ -1325,7 +1344,7 @@ void advance(Ctx &c, State &st, int64_t step0, int64_t nsteps, const StepOpts &s
         // (such tables and single-step tails take the passes below)
         if (c.plan.wave && !c.ex.rec && so.mode == kPlain && !isep && !rsep && nsteps - s >= 2 &&
             a.inj.xptr == c.L.src.xptr && a.rec.xptr == c.L.rec.xptr && a.ptab == c.L.ptab &&
-            !(c.plan.wave_auto && (int64_t)a.inj.cnt + a.rec.cnt > kWaveAutoEntries)) {
+            !(c.plan.wave_auto && ((int64_t)a.inj.cnt > kWaveAutoEntries || c.rec_extra > kWaveAutoEntries))) {
             const KernelKey &k = c.plan.key;
             a.u0 = st.cur;
             a.um = st.prev;

@@ -118,7 +118,9 @@ struct SweepArgs {
     uint32_t epoch;
     // Per-plane scalars of those passes, [nx][8]: the sponge profile px (as
     // bits), the plane's source entry range [ib, ie), its receiver entry range
-    // [rb, re), and flags (bit 0: sources, bit 1: receivers on the plane).
+    // [rb, re), flags (bit 0: sources, bit 1: receivers on the plane), and the
+    // first receiver entry's node (rec.yz[rb]) and output slot (rb when the
+    // receivers interpolate, else rec.id[rb]).
     const int32_t *ptab;
 };
 constexpr int kPlaneTab = 8;  // int32 slots per plane of SweepArgs::ptab

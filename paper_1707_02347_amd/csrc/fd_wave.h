@@ -140,9 +140,10 @@ struct WaveKernel {
         float um[PY];         // u^{n-1} at level 1's plane
         float q1[PY];         // q at level 1's plane (level 2 takes it M + E iterations later)
         float h1[HS];         // level-1 ring at level 2's plane (the neighbours' values)
-        int tab;              // lanes 0-5: level 1's plane, 6-11: level 2's (kPx .. kFl)
+        int tab;              // lanes 0-7: level 1's plane, 8-15: level 2's (kPx .. kRd)
     };
-    enum { kPx = 0, kIb = 1, kIe = 2, kRb = 3, kRe = 4, kFl = 5, kTab = 6 };
+    enum { kPx = 0, kIb = 1, kIe = 2, kRb = 3, kRe = 4, kFl = 5, kRy = 6, kRd = 7, kTab = 8 };
+    static_assert(kTab <= kPlaneTab, "per-plane table slots");
 
     struct Thread {
         int lane, wv, tile, nbt;  // nbt: the neighbour tile lane 0..3 polls (-1: none)
@@ -441,16 +442,25 @@ struct WaveKernel {
         }
     }
 
-    // Receivers on plane c of the level producing step `step`.
+    // Receivers on plane c of the level producing step `step`.  The first
+    // entry's node y0 and output slot d0 come with the per-plane table: a load
+    // here would wait for every prefetch issued before it, so a plane with a
+    // single entry is recorded without one.
     __device__ static __forceinline__ void record(const SweepArgs &a, const Thread &th, int step, int rb,
-                                                  int re, const float (&val)[PY])
+                                                  int re, int y0, int d0, const float (&val)[PY])
     {
         if (rb >= re) return;
         const int64_t row = a.rbase + (int64_t)a.rdir * step;
         const bool ent = a.rec.etr != nullptr;
         float *orow = ent ? a.rec.etr + row * a.rec.cnt : a.rec_out + row * a.rec.stride;
         const float rs = ent ? 1.0f : a.rscale;
-        for (int j = rb; j < re; ++j) {
+        {
+            const uint32_t p = (uint32_t)y0 * 4u;
+#pragma unroll
+            for (int r = 0; r < PY; ++r)
+                if (th.din[r] && th.bo[r] == p) orow[d0] = val[r] * rs;
+        }
+        for (int j = rb + 1; j < re; ++j) {
             const uint32_t p = (uint32_t)a.rec.yz[j] * 4u;
             const int dst = ent ? j : a.rec.id[j];
 #pragma unroll
@@ -517,7 +527,9 @@ struct WaveKernel {
         }
         update<PH + Q - M>(a, th, qa, S0, P.um, P.q1, __int_as_float(tab<1, kPx>(P.tab)), n1, a.step0, ib,
                           ie, o1v);
-        if (n1 && (f1 & 2)) record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), o1v);
+        if (n1 && (f1 & 2))
+            record(a, th, a.step0, tab<1, kRb>(P.tab), tab<1, kRe>(P.tab), tab<1, kRy>(P.tab), tab<1, kRd>(P.tab),
+                   o1v);
         const uint32_t sxy4 = (uint32_t)a.sxy * 4u;
         {
             const auto rw = wplane(a.o2, (uint32_t)c1 * sxy4, n1, sxy4);
@@ -543,7 +555,9 @@ struct WaveKernel {
         }
         update<PH + 1 + M>(a, th, qb, S1, up, q2, __int_as_float(tab<2, kPx>(P.tab)), n2, a.step0 + 1, ib, ie,
                            o2v);
-        if (n2 && (f2 & 2)) record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), o2v);
+        if (n2 && (f2 & 2))
+            record(a, th, a.step0 + 1, tab<2, kRb>(P.tab), tab<2, kRe>(P.tab), tab<2, kRy>(P.tab),
+                   tab<2, kRd>(P.tab), o2v);
         const auto ro = wplane(a.o1, (uint32_t)c2 * sxy4, n2, sxy4);
 #pragma unroll
         for (int r = 0; r < PY; ++r) bstore<kStream>(ro, th.bo[r], o2v[r]);

@@ -361,6 +361,10 @@ void check_wave(const Ctx &c, const KInfo &k, dim3 grid, dim3 block, const Sweep
         CHECK(px == a.px[x] && e[1] == ib && e[2] == ie && e[3] == rb && e[4] == re &&
                   e[5] == ((ie > ib ? 1 : 0) | (re > rb ? 2 : 0)),
               "per-plane table entry %d does not match the pass's tables", x);
+        if (re > rb)
+            CHECK(e[6] == a.rec.yz[rb] && e[7] == (a.rec.etr ? rb : a.rec.id[rb]),
+                  "per-plane table entry %d: first receiver entry (%d, %d) is not (%d, %d)", x, e[6], e[7],
+                  a.rec.yz[rb], a.rec.etr ? rb : a.rec.id[rb]);
     }
     CHECK(a.epoch >= 1, "epoch 0");
     uint32_t &last = epochs()[a.prog];

@@ -71,20 +71,28 @@ def test_tuner_keeps_fixed_fields(tmp_path, monkeypatch):
 
 def test_automatic_exchange_plan_runs_point_heavy_passes_single_level(tmp_path, monkeypatch):
     """A cached choice of the exchange form (the tuner run with the variant
-    fixed) serves automatic plans, but their passes with more than 64 point
-    entries run single-level: the workgroup walking those entries would hold
-    back its neighbours, which wait for its level 1.  An explicit request keeps
-    the exchange passes.  Every run equals the untiled sweep bit for bit."""
+    fixed) serves automatic plans, but their passes with more than 64 injected
+    entries (or 64 receiver entries beyond the first of each plane) run
+    single-level: the workgroup walking those entries through memory would hold
+    back its neighbours, which wait for its level 1.  A receiver line with one
+    receiver per plane keeps the exchange passes (a plane's first receiver
+    entry comes with the per-plane table), and an explicit request always does.
+    Every run equals the untiled sweep bit for bit."""
     monkeypatch.setenv("FD_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     shape = (96, 48, 70)  # a shape no other test tunes: the tuned choice stays in this process
-    v, h, so, nt, dt, src, _, amp = case(shape, so=8)
+    v, h, so, nt, dt, src1, _, amp1 = case(shape, so=8)
     tuned = api.autotune(tuple(v.shape), h, so, dt, sponge=6, vref=4500.0, variant=L.FD_VARIANT_WAVE)
     assert tuned["variant"] == L.FD_VARIANT_WAVE
-    for nrec, expect in ((12, L.FD_VARIANT_WAVE), (80, L.FD_VARIANT_STREAM)):
-        rec = synth.receiver_line(shape, nrec, depth=8)
+    line80 = synth.receiver_line(shape, 80, depth=8)          # 80 distinct x-planes
+    src80 = synth.receiver_line(shape, 80, depth=30, cross=12)
+    amp80 = amp1.repeat(1, 80).contiguous()
+    cases = ((src1, amp1, synth.receiver_line(shape, 12, depth=8), L.FD_VARIANT_WAVE),
+             (src1, amp1, line80, L.FD_VARIANT_WAVE),
+             (src80, amp80, synth.receiver_line(shape, 12, depth=8), L.FD_VARIANT_STREAM))
+    for src, amp, rec, expect in cases:
         base = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_NAIVE)
         auto = run(v, h, so, nt, dt, src, rec, amp)
-        assert api.last_config()["variant"] == expect, nrec
+        assert api.last_config()["variant"] == expect, (len(src), len(rec))
         assert torch.equal(auto["rec"], base["rec"]) and torch.equal(auto["u"], base["u"])
         explicit = run(v, h, so, nt, dt, src, rec, amp, variant=L.FD_VARIANT_WAVE, tile=tuned["tile"])
         assert api.last_config()["variant"] == L.FD_VARIANT_WAVE
