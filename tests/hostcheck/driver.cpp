@@ -518,6 +518,15 @@ int main()
         {{40, 38, 44}, 4, 24, opts()}, {{36, 44, 52}, 8, 21, opts()}, {{48, 40, 46}, 16, 18, opts()}};
     for (uint32_t f : {0u, (uint32_t)FD_FLAG_LOADS_STREAM, (uint32_t)FD_FLAG_LOADS_KEEP})
         batch_case("three orders flags " + std::to_string(f), three, false, FD_BATCH_GRAPH, f);
+    // the GPU suite's order: graph batches under both load policies, then the
+    // mixed batch issued directly and with a graph, three times over (the
+    // lane pool and its streams carry over from call to call)
+    for (int rep = 0; rep < 3; ++rep) {
+        for (uint32_t f : {(uint32_t)FD_FLAG_LOADS_STREAM, (uint32_t)FD_FLAG_LOADS_KEEP})
+            batch_case("sequence flags " + std::to_string(f), three, false, FD_BATCH_GRAPH, f);
+        batch_case("sequence direct", mix, false, 0, 0);
+        batch_case("sequence graph", mix, false, FD_BATCH_GRAPH, 0);
+    }
     // error paths
     {
         const fd_time t{10, stable_dt(g3)};
